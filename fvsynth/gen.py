@@ -1,0 +1,124 @@
+"""Seeded generators (numpy PCG64).  Recipes:
+
+* gmm(K, D, seed): rng = default_rng(seed); weights ~ Dirichlet(1_K), means ~ N(0,1)^{KxD},
+  variances ~ U[0.5, 2]^{KxD}, drawn in that order.  All three are cast to float32 and the
+  float32 arrays *are* the model.  The float64 weights are kept only for sampling labels.
+* frame(g, N, seed, outlier_frac): rng = default_rng(seed); labels ~ Cat(weights64);
+  x = mean[label] + sqrt(var[label]) * z, z ~ N(0, I); then round(outlier_frac*N) rows,
+  chosen without replacement, are replaced by U[-4, 4]^D.  Cast to float32.
+* batch_sizes(B, seed=1, lo=2000, hi=20000): default_rng(seed).integers(lo, hi+1, B).
+* serving_plan(...): 16 streams, Poisson arrivals at a rate per stream, resolutions
+  assigned round-robin from 320x240 .. 640x480, N = 8000 * area / (320*240).
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Gmm:
+    weights: np.ndarray    # [K] float32
+    means: np.ndarray      # [K, D] float32
+    variances: np.ndarray  # [K, D] float32
+    weights64: np.ndarray  # [K] float64 (sampling only)
+
+    @property
+    def K(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def D(self) -> int:
+        return int(self.means.shape[1])
+
+
+def gmm(K: int, D: int, seed: int = 0) -> Gmm:
+    rng = np.random.default_rng(seed)
+    w64 = rng.dirichlet(np.ones(K))
+    mu = rng.standard_normal((K, D))
+    var = rng.uniform(0.5, 2.0, (K, D))
+    return Gmm(weights=w64.astype(np.float32), means=mu.astype(np.float32),
+               variances=var.astype(np.float32), weights64=w64)
+
+
+def frame(g: Gmm, N: int, seed: int, outlier_frac: float = 0.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    K, D = g.K, g.D
+    labels = rng.choice(K, size=N, p=g.weights64 / g.weights64.sum())
+    z = rng.standard_normal((N, D))
+    mu = g.means.astype(np.float64)
+    sd = np.sqrt(g.variances.astype(np.float64))
+    x = mu[labels] + sd[labels] * z
+    n_out = int(round(outlier_frac * N))
+    if n_out > 0:
+        rows = rng.choice(N, size=n_out, replace=False)
+        x[rows] = rng.uniform(-4.0, 4.0, (n_out, D))
+    return np.ascontiguousarray(x.astype(np.float32))
+
+
+def batch_sizes(B: int, seed: int = 1, lo: int = 2000, hi: int = 20000) -> np.ndarray:
+    return np.random.default_rng(seed).integers(lo, hi + 1, B).astype(np.int64)
+
+
+def batch_frames(g: Gmm, sizes, seed0: int = 200, outlier_frac: float = 0.05):
+    """Frames of the given sizes, frame f drawn with seed seed0 + f.  Returns (X, offsets)."""
+    frames = [frame(g, int(n), seed0 + f, outlier_frac) for f, n in enumerate(sizes)]
+    offsets = np.zeros(len(frames) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([f.shape[0] for f in frames])
+    X = np.concatenate(frames, axis=0) if frames else np.zeros((0, g.D), np.float32)
+    return np.ascontiguousarray(X), offsets
+
+
+RESOLUTIONS = ((320, 240), (400, 300), (480, 360), (560, 420), (640, 480))
+
+
+def serving_plan(n_streams: int = 16, rate_hz: float = 30.0, duration_s: float = 22.0,
+                 pool: int = 8, base_n: int = 8000):
+    """Open-loop arrival schedule: list of (t_arrival_s, stream, pool_index), sorted by time,
+    plus the descriptor count of each stream.  Stream s uses default_rng(10000 + s) for its
+    exponential inter-arrival gaps; its pool frame p is drawn with seed 100000 + 100*s + p."""
+    sizes = []
+    events = []
+    for s in range(n_streams):
+        w, h = RESOLUTIONS[s % len(RESOLUTIONS)]
+        sizes.append(int(round(base_n * (w * h) / (320 * 240))))
+        rng = np.random.default_rng(10000 + s)
+        t, k = 0.0, 0
+        while True:
+            t += rng.exponential(1.0 / rate_hz)
+            if t >= duration_s:
+                break
+            events.append((t, s, k % pool))
+            k += 1
+    events.sort()
+    return events, sizes
+
+
+# Named workloads (K, D, N or batch recipe).  Descriptions only; data is drawn on demand.
+WORKLOADS = {
+    "c1_oracle_k64_d64_n2000": dict(K=64, D=64, gmm_seed=0, N=2000, frame_seed=0, outliers=0.0),
+    "c2_frame_k256_d64_n8000": dict(K=256, D=64, gmm_seed=0, N=8000, frame_seed=100, outliers=0.05),
+    "c4_batch64_k256_d64": dict(K=256, D=64, gmm_seed=0, B=64, sizes_seed=1, frame_seed0=200,
+                                outliers=0.05),
+    "c5_serving_k512_d80": dict(K=512, D=80, gmm_seed=0, streams=16, rate_hz=30.0),
+}
+
+
+def workload(name: str):
+    """Return (gmm, X, offsets) for a single-frame or batch workload."""
+    w = WORKLOADS[name]
+    g = gmm(w["K"], w["D"], w["gmm_seed"])
+    if "N" in w:
+        X = frame(g, w["N"], w["frame_seed"], w["outliers"])
+        return g, X, np.array([0, X.shape[0]], dtype=np.int64)
+    if "B" in w:
+        sizes = batch_sizes(w["B"], w["sizes_seed"])
+        X, off = batch_frames(g, sizes, w["frame_seed0"], w["outliers"])
+        return g, X, off
+    raise ValueError(f"workload {name} is not a frame or batch workload")
+
+
+def array_sha256(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()

@@ -1,0 +1,149 @@
+"""FP64 CPU oracle for Fisher-vector encoding -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this package.  The GPU library (``paper_1604_03498_amd``) never imports it, and the
+two share no code: the only common dependency is the seeded data generator ``fvsynth``.
+
+* ``fv_oracle.c`` -- plain sequential double-precision encoder (Algorithm 1 of the paper
+  plus the improved-FV normalisation), built with gcc into ``liboracle.so``.
+* ``brute.py``    -- 50-digit mpmath evaluation for tiny inputs.
+* ``metrics.py``  -- the error measures used to compare another encoder with this one.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fv_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NO_POWER = 1
+NO_L2 = 2
+
+class OracleLib:
+    """ctypes view of one build of the C oracle (the default build, or a test's own copy)."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        i64, i32, u32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_uint, ctypes.c_double
+        p = ctypes.c_void_p
+        lib.fvo_posteriors.argtypes = [i64, i32, i32, p, p, p, p, p]
+        lib.fvo_encode_tau.argtypes = [i64, i32, i32, p, p, p, p, u32, f64, p]
+        lib.fvo_encode.argtypes = [i64, i32, i32, p, p, p, p, u32, p]
+        lib.fvo_encode_batch.argtypes = [i32, p, i32, i32, p, p, p, p, u32, i32, p]
+        lib.fvo_max_threads.argtypes = []
+        for f in (lib.fvo_posteriors, lib.fvo_encode_tau, lib.fvo_encode, lib.fvo_encode_batch,
+                  lib.fvo_max_threads):
+            f.restype = ctypes.c_int
+        self.lib = lib
+        self.path = path
+
+    def posteriors(self, X, weights, means, variances) -> np.ndarray:
+        """gamma [N x K] in float64 (steps 1-4)."""
+        w, mu, var, K, D = _model(weights, means, variances)
+        X = _f32(X).reshape(-1, D)
+        out = np.empty((X.shape[0], K), dtype=np.float64)
+        rc = self.lib.fvo_posteriors(X.shape[0], K, D, _ptr(X), _ptr(w), _ptr(mu), _ptr(var),
+                                     _ptr(out))
+        if rc:
+            raise RuntimeError("oracle posteriors failed")
+        return out
+
+    def encode(self, X, weights, means, variances, flags: int = 0,
+               tau: float | None = None) -> np.ndarray:
+        """Fisher vector [2KD] in float64: [u (K x D) ; v (K x D)], signed-sqrt and L2 unless
+        flagged off."""
+        w, mu, var, K, D = _model(weights, means, variances)
+        X = _f32(X).reshape(-1, D)
+        out = np.empty(2 * K * D, dtype=np.float64)
+        t = -1.0 if tau is None else float(tau)
+        rc = self.lib.fvo_encode_tau(X.shape[0], K, D, _ptr(X), _ptr(w), _ptr(mu), _ptr(var),
+                                     int(flags), t, _ptr(out))
+        if rc:
+            raise RuntimeError("oracle encode failed")
+        return out
+
+    def encode_batch(self, X, offsets, weights, means, variances, flags: int = 0,
+                     nthreads: int = 1) -> np.ndarray:
+        """[B x 2KD]; frame b is rows offsets[b]:offsets[b+1].  nthreads spreads whole frames."""
+        w, mu, var, K, D = _model(weights, means, variances)
+        X = _f32(X).reshape(-1, D)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        B = off.shape[0] - 1
+        out = np.empty((B, 2 * K * D), dtype=np.float64)
+        rc = self.lib.fvo_encode_batch(B, _ptr(off), K, D, _ptr(X), _ptr(w), _ptr(mu), _ptr(var),
+                                       int(flags), int(nthreads), _ptr(out))
+        if rc:
+            raise RuntimeError("oracle encode_batch failed")
+        return out
+
+    def max_threads(self) -> int:
+        return int(self.lib.fvo_max_threads())
+
+
+_default = None
+
+
+def _load() -> OracleLib:
+    global _default
+    if _default is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        _default = OracleLib(_LIB)
+    return _default
+
+
+def compile_variant(src_text: str, out_path: str) -> OracleLib:
+    """Compile a (test-modified) copy of the oracle source and load it.  Used by the tests that
+    plant mistakes in the oracle to show that the pins catch them."""
+    c_path = out_path + ".c"
+    with open(c_path, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+                           "-shared", c_path, "-o", out_path, "-lm"])
+    return OracleLib(out_path)
+
+
+def source() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _model(weights, means, variances):
+    w, mu, var = _f32(weights), _f32(means), _f32(variances)
+    K, D = mu.shape
+    assert w.shape == (K,) and var.shape == (K, D)
+    return w, mu, var, K, D
+
+
+def posteriors(X, weights, means, variances) -> np.ndarray:
+    return _load().posteriors(X, weights, means, variances)
+
+
+def encode(X, weights, means, variances, flags: int = 0, tau: float | None = None) -> np.ndarray:
+    return _load().encode(X, weights, means, variances, flags, tau)
+
+
+def encode_batch(X, offsets, weights, means, variances, flags: int = 0,
+                 nthreads: int = 1) -> np.ndarray:
+    return _load().encode_batch(X, offsets, weights, means, variances, flags, nthreads)
+
+
+def max_threads() -> int:
+    return _load().max_threads()
+
+
+def encode_gmm(X, g, flags: int = 0, tau: float | None = None) -> np.ndarray:
+    return encode(X, g.weights, g.means, g.variances, flags, tau)
