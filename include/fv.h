@@ -1,0 +1,137 @@
+/*
+ * libfv -- Fisher-vector encoding of local descriptors against a diagonal GMM, on AMD
+ * Instinct MI355X (gfx950).  C ABI: plain pointers and sizes, no C++ or framework types.
+ *
+ * The operation (Ma et al., "GPU-FV: Realtime Fisher Vector and Its Applications in Video
+ * Monitoring", ICMR 2016, Sec. 2.1 and Algorithm 1; normalisation of the improved Fisher
+ * vector of Perronnin et al. / Sanchez et al. that the paper cites and that its experiments
+ * use via "the same encoding scheme as VLFeat", Sec. 4):
+ *
+ *   input   N descriptors x_t in R^D; a K-component diagonal GMM (weights w_k, means mu_k,
+ *           variances var_k = sigma_k^2)
+ *   gamma   gamma_tk = w_k N(x_t; mu_k, var_k) / sum_j w_j N(x_t; mu_j, var_j)
+ *           (the per-descriptor posterior / soft assignment, Algorithm 1 first loop)
+ *   u_kd    = 1/(N sqrt(w_k))   sum_t gamma_tk (x_td - mu_kd) / sigma_kd
+ *   v_kd    = 1/(N sqrt(2 w_k)) sum_t gamma_tk [((x_td - mu_kd) / sigma_kd)^2 - 1]
+ *           (Algorithm 1 second loop, with the Fisher-information scaling)
+ *   phi     = [u ; v], each block component-major (index k*D + d), length 2*K*D
+ *   unless FV_NO_POWER_NORM: phi_i <- sign(phi_i) sqrt(|phi_i|)
+ *   unless FV_NO_L2_NORM:    phi   <- phi / ||phi||_2  (left unscaled when the norm is 0)
+ *
+ * No posterior threshold is applied (every term is accumulated).  A frame with N = 0 encodes
+ * to 2KD zeros.  Non-finite descriptor values are not checked: NaN propagates to the output.
+ *
+ * Return codes: FV_OK (0), FV_PENDING (1), or a negative FV_E_* code; fv_strerror() names
+ * them.  No C++ exception crosses this interface.  Functions are thread-safe unless stated.
+ */
+#ifndef FV_H_
+#define FV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------------- */
+#define FV_OK 0
+#define FV_PENDING 1
+#define FV_E_INVAL (-1)       /* bad argument (sizes, null pointers, GMM values, flags) */
+#define FV_E_NOMEM (-2)       /* device or pinned host allocation failed */
+#define FV_E_DEVICE (-3)      /* a HIP runtime call failed; see fv_last_device_error() */
+#define FV_E_BUDGET (-4)      /* a request can never fit the server's device-memory budget */
+#define FV_E_AGAIN (-5)       /* server queue full; retry later */
+#define FV_E_NOTFOUND (-6)    /* unknown server ticket */
+#define FV_E_TIMEOUT (-7)     /* request exceeded its deadline */
+#define FV_E_UNSUPPORTED (-8) /* valid request outside this build's limits (see fv_limits) */
+
+/* ---- arithmetic forms ------------------------------------------------------------------ */
+#define FV_PREC_FP32 0        /* both contractions on FP32 MFMA, FP32 accumulate */
+#define FV_PREC_BF16_SPLIT 1  /* bf16 hi/lo operands, 3 products (hi*hi + hi*lo + lo*hi) */
+#define FV_PREC_FP16_SPLIT 2  /* fp16 hi/lo operands, 3 products */
+#define FV_PREC_BF16 3        /* plain bf16 operands (accuracy control only) */
+
+/* ---- flags ----------------------------------------------------------------------------- */
+#define FV_X_DEVICE 1u        /* X (and offsets' rows) live in device memory; else host memory */
+#define FV_OUT_DEVICE 2u      /* out lives in device memory; else host memory */
+#define FV_NO_POWER_NORM 4u   /* skip the signed square root */
+#define FV_NO_L2_NORM 8u      /* skip the L2 normalisation */
+#define FV_ASYNC 16u          /* return after enqueueing on the stream, without waiting */
+
+typedef struct fv_gmm fv_gmm;
+
+/* Size limits of this build: K <= max_K, D <= max_D (any K >= 1, D >= 1 below them). */
+void fv_limits(int* max_K, int* max_D);
+
+/*
+ * Load a diagonal GMM onto device `device` (Algorithm 1, "Compute sqrt(sigma^-1)"; here the
+ * whole per-model constant set is evaluated once, in double precision, on the host:
+ * 1/sigma, 1/sigma^2, the E-step operand [mu/sigma^2 ; -1/(2 sigma^2)] and offsets
+ * ln w_k - 1/2 sum_d ln sigma^2_kd - 1/2 sum_d mu_kd^2/sigma^2_kd, and the block scales
+ * 1/sqrt(w_k), 1/sqrt(2 w_k)).
+ *   priors    [K]     host float32, every entry finite and > 0; used as given (no
+ *                     renormalisation to sum 1)
+ *   means     [K x D] host float32 row-major (component-major), finite
+ *   variances [K x D] host float32 row-major, finite and > 0 (variances, not std devs)
+ *   out       receives an opaque, immutable handle; share it freely between threads
+ * The caller keeps ownership of its arrays and may free them on return.
+ * Errors: FV_E_INVAL (null pointer, K < 1, D < 1, a bad value), FV_E_UNSUPPORTED (K or D over
+ * the limits), FV_E_NOMEM, FV_E_DEVICE.  On error *out is set to NULL.
+ */
+int fv_gmm_load(int K, int D, const float* priors, const float* means, const float* variances,
+                int device, fv_gmm** out);
+
+/* Release a handle (NULL is accepted).  No call using it may still be in flight. */
+int fv_gmm_free(fv_gmm* gmm);
+
+/* K, D and device of a handle (any pointer may be NULL). */
+int fv_gmm_info(const fv_gmm* gmm, int* K, int* D, int* device);
+
+/*
+ * Encode one frame: X [N x D] float32 row-major -> out [2*K*D] float32, laid out as above.
+ *   flags      FV_X_DEVICE / FV_OUT_DEVICE say where X and out live (host otherwise);
+ *              FV_NO_POWER_NORM / FV_NO_L2_NORM drop the normalisation steps;
+ *              FV_ASYNC returns once the work is enqueued on `hip_stream` -- the caller then
+ *              keeps X and out alive (host buffers too) until that stream is synchronised.
+ *   hip_stream a hipStream_t (NULL = the default stream) on the handle's device.
+ * The caller owns X and out.  N = 0 writes zeros.  Device X must be 4-byte aligned; a
+ * 16-byte aligned X with D % 4 == 0 takes the vector-load path.
+ * Errors: FV_E_INVAL (null pointers, N < 0, bad precision or flags), FV_E_NOMEM,
+ * FV_E_DEVICE.
+ */
+int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int precision,
+              unsigned flags, void* hip_stream);
+
+/*
+ * Encode B frames in one launch sequence.  Frame b is rows [offsets[b], offsets[b+1]) of
+ * X [offsets[B] x D]; out is [B x 2*K*D].  `offsets` is a HOST array of B+1 int64 values
+ * with offsets[0] == 0 and offsets non-decreasing (else FV_E_INVAL).  Frames are split into
+ * chunks relative to their own first row, so a frame's result does not depend on the other
+ * frames in the batch (bitwise).  Other arguments as fv_encode.
+ */
+int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, int B, float* out,
+                    int precision, unsigned flags, void* hip_stream);
+
+/*
+ * Kernel timing (instrumentation for benchmarks and profilers).  fv_kernel_timing(1) resets
+ * the counters and starts bracketing every launch of libfv's kernels with HIP events on the
+ * stream the kernel is launched on; fv_kernel_timing(0) stops.  fv_kernel_timing_read waits
+ * for the recorded events and returns the summed device duration (ms) and the launch count
+ * of kernel class `which` (0 = statistics kernel, 1 = finalize kernels) since the reset.
+ * Errors: FV_E_INVAL (bad `which`), FV_E_DEVICE.
+ */
+int fv_kernel_timing(int enable);
+int fv_kernel_timing_read(int which, double* total_ms, int64_t* launches);
+
+/* Static description of a status code. */
+const char* fv_strerror(int code);
+
+/* The last HIP error code seen by the calling thread inside libfv (0 if none). */
+int fv_last_device_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FV_H_ */

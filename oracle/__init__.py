@@ -24,6 +24,17 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 NO_POWER = 1
 NO_L2 = 2
 
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (strict IEEE double, no contraction, OpenMP over frames)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+            "-Wall", "-Wextra", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
 class OracleLib:
     """ctypes view of one build of the C oracle (the default build, or a test's own copy)."""
 

@@ -1,0 +1,545 @@
+// libfv host runtime: C ABI entry points, GMM constant precompute (double precision),
+// per-stream workspaces, and the launch sequences of the encoder.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "fv.h"
+#include "fv_internal.h"
+
+struct fv_gmm {
+  int K = 0, D = 0, device = 0;
+  fv::Consts c{};
+  void* dev_block = nullptr;  // one allocation holding every constant array
+};
+
+namespace {
+
+thread_local int t_last_hip_error = 0;
+
+constexpr unsigned kAllFlags =
+    FV_X_DEVICE | FV_OUT_DEVICE | FV_NO_POWER_NORM | FV_NO_L2_NORM | FV_ASYNC;
+
+int hip_fail(hipError_t e) {
+  t_last_hip_error = (int)e;
+  return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? FV_E_NOMEM : FV_E_DEVICE;
+}
+
+#define FV_HIP(expr)                          \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+// Makes `device` current for the lifetime of the guard and restores the caller's device.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int device) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    status_ = (prev_ == device) ? hipSuccess : hipSetDevice(device);
+  }
+  ~DeviceGuard() {
+    if (prev_ >= 0 && status_ == hipSuccess) (void)hipSetDevice(prev_);
+  }
+  hipError_t status() const { return status_; }
+
+ private:
+  int prev_ = -1;
+  hipError_t status_ = hipSuccess;
+};
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+int device_cu_count(int device) {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(device);
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0)
+    n = 256;
+  cache[device] = n;
+  return n;
+}
+
+// Device scratch (partials, tables, staging) and pinned host staging, cached per (device,
+// stream).  Work on one stream is ordered, so reusing the buffers between calls is safe; a
+// buffer is only replaced after the stream has drained.
+struct Workspace {
+  std::mutex mu;
+  char* dev = nullptr;
+  size_t dev_cap = 0;
+  char* pinned = nullptr;
+  size_t pin_cap = 0;
+  hipEvent_t pin_done = nullptr;  // last H2D copy out of `pinned`
+  bool pin_pending = false;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+
+Workspace* workspace_for(int device, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto& p = g_ws[{device, s}];
+  if (!p) p.reset(new (std::nothrow) Workspace());
+  return p.get();
+}
+
+int ensure_dev(Workspace* ws, size_t need, hipStream_t s) {
+  if (need <= ws->dev_cap) return FV_OK;
+  if (ws->dev) {
+    FV_HIP(hipStreamSynchronize(s));
+    FV_HIP(hipFree(ws->dev));
+    ws->dev = nullptr;
+    ws->dev_cap = 0;
+  }
+  size_t cap = std::max(need, (size_t)(1u << 20));
+  cap = align256(cap + cap / 4);
+  FV_HIP(hipMalloc(&ws->dev, cap));
+  ws->dev_cap = cap;
+  return FV_OK;
+}
+
+int ensure_pinned(Workspace* ws, size_t need) {
+  if (ws->pin_pending) {
+    FV_HIP(hipEventSynchronize(ws->pin_done));
+    ws->pin_pending = false;
+  }
+  if (!ws->pin_done) FV_HIP(hipEventCreateWithFlags(&ws->pin_done, hipEventDisableTiming));
+  if (need <= ws->pin_cap) return FV_OK;
+  if (ws->pinned) {
+    FV_HIP(hipHostFree(ws->pinned));
+    ws->pinned = nullptr;
+    ws->pin_cap = 0;
+  }
+  size_t cap = align256(std::max(need, (size_t)(64u << 10)) * 2);
+  FV_HIP(hipHostMalloc(&ws->pinned, cap, hipHostMallocDefault));
+  ws->pin_cap = cap;
+  return FV_OK;
+}
+
+bool finite_f(float v) { return std::isfinite(v); }
+
+// Chunk length for a single frame: enough items to give every CU work, in whole tiles.
+int single_frame_chunk(int64_t N, int device, int W) {
+  const int64_t target = (int64_t)device_cu_count(device) * std::max(1, 8 / W);
+  int64_t tiles = (N + fv::kTile - 1) / fv::kTile;
+  int64_t per = (tiles + target - 1) / target;
+  if (per < 1) per = 1;
+  const int64_t maxP = (int64_t)1 << 20;
+  int64_t P = per * fv::kTile;
+  return (int)std::min(P, maxP);
+}
+
+int batch_chunk() {
+  static int P = [] {
+    int v = 1024;
+    if (const char* e = std::getenv("FV_BATCH_CHUNK")) {
+      int x = std::atoi(e);
+      if (x >= fv::kTile) v = (x / fv::kTile) * fv::kTile;
+    }
+    return v;
+  }();
+  return P;
+}
+
+// ---- optional kernel timing: event pairs recorded around launches on the launch stream
+struct TimingState {
+  std::mutex mu;
+  bool enabled = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+  std::vector<hipEvent_t> pool;
+  double total_ms[2] = {0.0, 0.0};
+  int64_t launches[2] = {0, 0};
+};
+TimingState g_timing;
+
+hipEvent_t timing_event() {
+  hipEvent_t e = nullptr;
+  if (!g_timing.pool.empty()) {
+    e = g_timing.pool.back();
+    g_timing.pool.pop_back();
+    return e;
+  }
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records a start event when timing is on; returns it (or null).
+hipEvent_t timing_begin(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (!g_timing.enabled) return nullptr;
+  hipEvent_t e = timing_event();
+  if (e && hipEventRecord(e, s) != hipSuccess) {
+    g_timing.pool.push_back(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void timing_end(hipEvent_t start, int which, hipStream_t s) {
+  if (!start) return;
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  hipEvent_t e = timing_event();
+  if (!e || hipEventRecord(e, s) != hipSuccess) {
+    g_timing.pool.push_back(start);
+    if (e) g_timing.pool.push_back(e);
+    return;
+  }
+  g_timing.pending[which].push_back({start, e});
+}
+
+}  // namespace
+
+extern "C" {
+
+int fv_kernel_timing(int enable) {
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  for (int w = 0; w < 2; ++w) {
+    for (auto& pr : g_timing.pending[w]) {
+      (void)hipEventSynchronize(pr.second);
+      g_timing.pool.push_back(pr.first);
+      g_timing.pool.push_back(pr.second);
+    }
+    g_timing.pending[w].clear();
+    g_timing.total_ms[w] = 0.0;
+    g_timing.launches[w] = 0;
+  }
+  g_timing.enabled = enable != 0;
+  return FV_OK;
+}
+
+int fv_kernel_timing_read(int which, double* total_ms, int64_t* launches) {
+  if (which < 0 || which > 1) return FV_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  for (auto& pr : g_timing.pending[which]) {
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e != hipSuccess) return hip_fail(e);
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) return hip_fail(e);
+    g_timing.total_ms[which] += ms;
+    g_timing.launches[which] += 1;
+    g_timing.pool.push_back(pr.first);
+    g_timing.pool.push_back(pr.second);
+  }
+  g_timing.pending[which].clear();
+  if (total_ms) *total_ms = g_timing.total_ms[which];
+  if (launches) *launches = g_timing.launches[which];
+  return FV_OK;
+}
+
+void fv_limits(int* max_K, int* max_D) {
+  if (max_K) *max_K = fv::kMaxK;
+  if (max_D) *max_D = fv::kMaxD;
+}
+
+const char* fv_strerror(int code) {
+  switch (code) {
+    case FV_OK: return "ok";
+    case FV_PENDING: return "pending";
+    case FV_E_INVAL: return "invalid argument";
+    case FV_E_NOMEM: return "out of memory";
+    case FV_E_DEVICE: return "device (HIP runtime) error";
+    case FV_E_BUDGET: return "request exceeds the device-memory budget";
+    case FV_E_AGAIN: return "queue full, try again";
+    case FV_E_NOTFOUND: return "unknown ticket";
+    case FV_E_TIMEOUT: return "deadline exceeded";
+    case FV_E_UNSUPPORTED: return "unsupported size or form";
+    default: return "unknown status";
+  }
+}
+
+int fv_last_device_error(void) { return t_last_hip_error; }
+
+int fv_gmm_load(int K, int D, const float* priors, const float* means, const float* variances,
+                int device, fv_gmm** out) {
+  if (!out) return FV_E_INVAL;
+  *out = nullptr;
+  if (K < 1 || D < 1 || !priors || !means || !variances) return FV_E_INVAL;
+  for (int k = 0; k < K; ++k)
+    if (!finite_f(priors[k]) || !(priors[k] > 0.f)) return FV_E_INVAL;
+  const size_t KD = (size_t)K * D;
+  for (size_t i = 0; i < KD; ++i) {
+    if (!finite_f(means[i])) return FV_E_INVAL;
+    if (!finite_f(variances[i]) || !(variances[i] > 0.f)) return FV_E_INVAL;
+  }
+  if (K > fv::kMaxK || D > fv::kMaxD) return FV_E_UNSUPPORTED;
+  int ndev = 0;
+  const hipError_t de = hipGetDeviceCount(&ndev);
+  if (de != hipSuccess) return hip_fail(de);
+  if (device < 0 || device >= ndev) return FV_E_INVAL;
+
+  fv::Consts c{};
+  c.K = K;
+  c.D = D;
+  c.W = 1;
+  while (c.W * fv::kCompsPerWave < K) c.W *= 2;
+  c.Kp = c.W * fv::kCompsPerWave;
+  c.DP = ((D + 15) / 16) * 16;
+  const int Kp = c.Kp, DP = c.DP;
+
+  // ---- precompute in double (the paper's "compute sqrt(sigma^-1)" step, widened to every
+  // per-model constant the kernels need)
+  const double LOG2E = 1.4426950408889634073599246810019;
+  std::vector<float> A((size_t)2 * DP * Kp, 0.f), cc((size_t)Kp, -1e30f);
+  std::vector<uint16_t> abh(A.size(), 0), abl(A.size(), 0), ahh(A.size(), 0), ahl(A.size(), 0);
+  std::vector<double> mu64(KD), isd64(KD), ivar64(KD), cu64(K), cv64(K);
+  for (int k = 0; k < K; ++k) {
+    double logdet = 0.0, quad = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const double m = means[(size_t)k * D + d];
+      const double v = variances[(size_t)k * D + d];
+      const double iv = 1.0 / v;
+      A[(size_t)d * Kp + k] = (float)(m * iv * LOG2E);
+      A[(size_t)(DP + d) * Kp + k] = (float)(-0.5 * iv * LOG2E);
+      logdet += std::log(v);
+      quad += m * m * iv;
+      mu64[(size_t)k * D + d] = m;
+      isd64[(size_t)k * D + d] = 1.0 / std::sqrt(v);
+      ivar64[(size_t)k * D + d] = iv;
+    }
+    const double w = priors[k];
+    cc[k] = (float)((std::log(w) - 0.5 * logdet - 0.5 * quad) * LOG2E);
+    cu64[k] = 1.0 / std::sqrt(w);
+    cv64[k] = 1.0 / std::sqrt(2.0 * w);
+  }
+
+  // ---- one device block: A32 | c32 | 4 x 16-bit splits (filled by the split forms) | doubles
+  const size_t nA = A.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t oA = take(nA * 4), oc = take((size_t)Kp * 4);
+  const size_t oBH = take(nA * 2), oBL = take(nA * 2), oHH = take(nA * 2), oHL = take(nA * 2);
+  const size_t oMu = take(KD * 8), oIsd = take(KD * 8), oIvar = take(KD * 8);
+  const size_t oCu = take((size_t)K * 8), oCv = take((size_t)K * 8);
+  const size_t total = off;
+
+  DeviceGuard g(device);
+  if (g.status() != hipSuccess) return hip_fail(g.status());
+  std::unique_ptr<fv_gmm> h(new (std::nothrow) fv_gmm());
+  if (!h) return FV_E_NOMEM;
+  char* blk = nullptr;
+  FV_HIP(hipMalloc(&blk, total));
+  std::vector<char> host(total, 0);
+  std::memcpy(host.data() + oA, A.data(), nA * 4);
+  std::memcpy(host.data() + oc, cc.data(), (size_t)Kp * 4);
+  std::memcpy(host.data() + oBH, abh.data(), nA * 2);
+  std::memcpy(host.data() + oBL, abl.data(), nA * 2);
+  std::memcpy(host.data() + oHH, ahh.data(), nA * 2);
+  std::memcpy(host.data() + oHL, ahl.data(), nA * 2);
+  std::memcpy(host.data() + oMu, mu64.data(), KD * 8);
+  std::memcpy(host.data() + oIsd, isd64.data(), KD * 8);
+  std::memcpy(host.data() + oIvar, ivar64.data(), KD * 8);
+  std::memcpy(host.data() + oCu, cu64.data(), (size_t)K * 8);
+  std::memcpy(host.data() + oCv, cv64.data(), (size_t)K * 8);
+  hipError_t e = hipMemcpy(blk, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(blk);
+    return hip_fail(e);
+  }
+  c.A32 = reinterpret_cast<const float*>(blk + oA);
+  c.c32 = reinterpret_cast<const float*>(blk + oc);
+  c.Abf_hi = reinterpret_cast<const uint16_t*>(blk + oBH);
+  c.Abf_lo = reinterpret_cast<const uint16_t*>(blk + oBL);
+  c.Ah_hi = reinterpret_cast<const uint16_t*>(blk + oHH);
+  c.Ah_lo = reinterpret_cast<const uint16_t*>(blk + oHL);
+  c.mu64 = reinterpret_cast<const double*>(blk + oMu);
+  c.isd64 = reinterpret_cast<const double*>(blk + oIsd);
+  c.ivar64 = reinterpret_cast<const double*>(blk + oIvar);
+  c.cu64 = reinterpret_cast<const double*>(blk + oCu);
+  c.cv64 = reinterpret_cast<const double*>(blk + oCv);
+  h->K = K;
+  h->D = D;
+  h->device = device;
+  h->c = c;
+  h->dev_block = blk;
+  *out = h.release();
+  return FV_OK;
+}
+
+int fv_gmm_free(fv_gmm* gmm) {
+  if (!gmm) return FV_OK;
+  int rc = FV_OK;
+  {
+    DeviceGuard g(gmm->device);
+    if (gmm->dev_block) {
+      hipError_t e = hipFree(gmm->dev_block);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+  }
+  delete gmm;
+  return rc;
+}
+
+int fv_gmm_info(const fv_gmm* gmm, int* K, int* D, int* device) {
+  if (!gmm) return FV_E_INVAL;
+  if (K) *K = gmm->K;
+  if (D) *D = gmm->D;
+  if (device) *device = gmm->device;
+  return FV_OK;
+}
+
+int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int precision,
+              unsigned flags, void* hip_stream) {
+  if (!gmm || !out || N < 0 || (N > 0 && !X)) return FV_E_INVAL;
+  if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
+  if (flags & ~kAllFlags) return FV_E_INVAL;
+  if (precision != FV_PREC_FP32) return FV_E_UNSUPPORTED;
+  const fv::Consts& c = gmm->c;
+  if (N > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
+  DeviceGuard g(gmm->device);
+  if (g.status() != hipSuccess) return hip_fail(g.status());
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  Workspace* ws = workspace_for(gmm->device, s);
+  if (!ws) return FV_E_NOMEM;
+  std::lock_guard<std::mutex> lk(ws->mu);
+
+  const int P = N > 0 ? single_frame_chunk(N, gmm->device, c.W) : fv::kTile;
+  const int64_t n_items64 = N > 0 ? (N + P - 1) / P : 0;
+  const int n_items = (int)n_items64;
+  const int nblk = fv::finalize_blocks(c);
+  const size_t out_len = (size_t)2 * c.K * c.D;
+  const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
+  const size_t b_norm = align256((size_t)nblk * 8);
+  const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)N * c.D * 4);
+  const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256(out_len * 4);
+  int rc = ensure_dev(ws, b_part + b_norm + b_x + b_out, s);
+  if (rc) return rc;
+  float* partials = reinterpret_cast<float*>(ws->dev);
+  double* normpart = reinterpret_cast<double*>(ws->dev + b_part);
+  float* xdev = reinterpret_cast<float*>(ws->dev + b_part + b_norm);
+  float* odev = reinterpret_cast<float*>(ws->dev + b_part + b_norm + b_x);
+
+  const float* Xd = X;
+  if (!(flags & FV_X_DEVICE) && N > 0) {
+    FV_HIP(hipMemcpyAsync(xdev, X, (size_t)N * c.D * 4, hipMemcpyHostToDevice, s));
+    Xd = xdev;
+  }
+  float* Od = (flags & FV_OUT_DEVICE) ? out : odev;
+  const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
+  if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
+
+  hipEvent_t t0 = n_items > 0 ? timing_begin(s) : nullptr;
+  FV_HIP(fv::launch_stats(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
+  timing_end(t0, 0, s);
+  fv::Frame single{N, 0, n_items};
+  hipEvent_t t1 = timing_begin(s);
+  FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, flags, Od, normpart, s));
+  timing_end(t1, 1, s);
+  if (!(flags & FV_OUT_DEVICE))
+    FV_HIP(hipMemcpyAsync(out, Od, out_len * 4, hipMemcpyDeviceToHost, s));
+  if (!(flags & FV_ASYNC)) FV_HIP(hipStreamSynchronize(s));
+  return FV_OK;
+}
+
+int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, int B, float* out,
+                    int precision, unsigned flags, void* hip_stream) {
+  if (!gmm || !offsets || B < 0 || (B > 0 && !out)) return FV_E_INVAL;
+  if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
+  if (flags & ~kAllFlags) return FV_E_INVAL;
+  if (offsets[0] != 0) return FV_E_INVAL;
+  for (int b = 0; b < B; ++b)
+    if (offsets[b + 1] < offsets[b]) return FV_E_INVAL;
+  if (B == 0) return FV_OK;
+  const int64_t rows = offsets[B];
+  if (rows > 0 && !X) return FV_E_INVAL;
+  if (precision != FV_PREC_FP32) return FV_E_UNSUPPORTED;
+  const fv::Consts& c = gmm->c;
+  if (rows > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
+
+  // Frame-relative chunking: frame b's chunk j covers its rows [j*P, (j+1)*P).
+  const int P = batch_chunk();
+  std::vector<fv::Frame> frames((size_t)B);
+  int64_t n_items64 = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t n = offsets[b + 1] - offsets[b];
+    const int64_t ni = (n + P - 1) / P;
+    frames[b] = fv::Frame{n, (int32_t)n_items64, (int32_t)ni};
+    n_items64 += ni;
+  }
+  if (n_items64 > (int64_t)1 << 30) return FV_E_UNSUPPORTED;
+  const int n_items = (int)n_items64;
+
+  DeviceGuard g(gmm->device);
+  if (g.status() != hipSuccess) return hip_fail(g.status());
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  Workspace* ws = workspace_for(gmm->device, s);
+  if (!ws) return FV_E_NOMEM;
+  std::lock_guard<std::mutex> lk(ws->mu);
+
+  const int nblk = fv::finalize_blocks(c);
+  const size_t out_len = (size_t)2 * c.K * c.D;
+  const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
+  const size_t b_norm = align256((size_t)B * nblk * 8);
+  const size_t b_frames = align256((size_t)B * sizeof(fv::Frame));
+  const size_t b_items = align256((size_t)n_items * sizeof(fv::Item));
+  const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)rows * c.D * 4);
+  const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256((size_t)B * out_len * 4);
+  int rc = ensure_dev(ws, b_part + b_norm + b_frames + b_items + b_x + b_out, s);
+  if (rc) return rc;
+  rc = ensure_pinned(ws, b_frames + b_items);
+  if (rc) return rc;
+  char* base = ws->dev;
+  float* partials = reinterpret_cast<float*>(base);
+  double* normpart = reinterpret_cast<double*>(base + b_part);
+  fv::Frame* dframes = reinterpret_cast<fv::Frame*>(base + b_part + b_norm);
+  fv::Item* ditems = reinterpret_cast<fv::Item*>(base + b_part + b_norm + b_frames);
+  float* xdev = reinterpret_cast<float*>(base + b_part + b_norm + b_frames + b_items);
+  float* odev = reinterpret_cast<float*>(base + b_part + b_norm + b_frames + b_items + b_x);
+
+  // work table in pinned memory, then one H2D copy
+  fv::Frame* hframes = reinterpret_cast<fv::Frame*>(ws->pinned);
+  fv::Item* hitems = reinterpret_cast<fv::Item*>(ws->pinned + b_frames);
+  std::memcpy(hframes, frames.data(), (size_t)B * sizeof(fv::Frame));
+  {
+    int64_t i = 0;
+    for (int b = 0; b < B; ++b)
+      for (int32_t q = 0; q < frames[b].nitems; ++q, ++i) {
+        const int64_t r0 = (int64_t)q * P;
+        const int64_t nr = std::min<int64_t>(P, frames[b].nrows - r0);
+        hitems[i] = fv::Item{offsets[b] + r0, (int32_t)nr, 0};
+      }
+  }
+  FV_HIP(hipMemcpyAsync(dframes, ws->pinned, b_frames + b_items, hipMemcpyHostToDevice, s));
+  FV_HIP(hipEventRecord(ws->pin_done, s));
+  ws->pin_pending = true;
+
+  const float* Xd = X;
+  if (!(flags & FV_X_DEVICE) && rows > 0) {
+    FV_HIP(hipMemcpyAsync(xdev, X, (size_t)rows * c.D * 4, hipMemcpyHostToDevice, s));
+    Xd = xdev;
+  }
+  if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
+  float* Od = (flags & FV_OUT_DEVICE) ? out : odev;
+  const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
+  const int resident = device_cu_count(gmm->device) * std::max(1, 8 / c.W);
+  const int grid = std::max(1, std::min(n_items, resident));
+  hipEvent_t t0 = n_items > 0 ? timing_begin(s) : nullptr;
+  FV_HIP(fv::launch_stats(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid, partials, s));
+  timing_end(t0, 0, s);
+  hipEvent_t t1 = timing_begin(s);
+  FV_HIP(fv::launch_finalize(c, partials, dframes, fv::Frame{0, 0, 0}, B, flags, Od, normpart, s));
+  timing_end(t1, 1, s);
+  if (!(flags & FV_OUT_DEVICE))
+    FV_HIP(hipMemcpyAsync(out, Od, (size_t)B * out_len * 4, hipMemcpyDeviceToHost, s));
+  if (!(flags & FV_ASYNC)) FV_HIP(hipStreamSynchronize(s));
+  return FV_OK;
+}
+
+}  // extern "C"

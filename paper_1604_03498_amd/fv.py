@@ -1,0 +1,246 @@
+"""ctypes binding of the libfv C ABI (include/fv.h).  Argument marshalling only.
+
+Names mirror the C entry points without the ``fv_`` prefix.  Host arrays are numpy
+arrays; device arrays and streams are torch tensors / ``torch.cuda.Stream`` objects (torch
+is used for device memory and streams, nothing else).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+OK, PENDING = 0, 1
+E_INVAL, E_NOMEM, E_DEVICE, E_BUDGET = -1, -2, -3, -4
+E_AGAIN, E_NOTFOUND, E_TIMEOUT, E_UNSUPPORTED = -5, -6, -7, -8
+PREC_FP32, PREC_BF16_SPLIT, PREC_FP16_SPLIT, PREC_BF16 = 0, 1, 2, 3
+X_DEVICE, OUT_DEVICE, NO_POWER_NORM, NO_L2_NORM, ASYNC = 1, 2, 4, 8, 16
+
+EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "fv_encode",
+                    "fv_encode_batch", "fv_kernel_timing", "fv_kernel_timing_read",
+                    "fv_strerror", "fv_last_device_error")
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfv.so")
+_lib = None
+
+
+class FvError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = strerror(code) if _lib is not None else str(code)
+        if code == E_DEVICE and _lib is not None:
+            msg += f" (hip error {last_device_error()})"
+        super().__init__(f"{what}: {msg} [{code}]" if what else f"{msg} [{code}]")
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libfv.so (built in-tree by paper_1604_03498_amd.build).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"libfv.so not built ({_LIB_PATH}); run python -m paper_1604_03498_amd.build")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint
+    lib.fv_limits.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.fv_limits.restype = None
+    lib.fv_gmm_load.argtypes = [i32, i32, vp, vp, vp, i32, ctypes.POINTER(vp)]
+    lib.fv_gmm_free.argtypes = [vp]
+    lib.fv_gmm_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.fv_encode.argtypes = [vp, vp, i64, vp, i32, u32, vp]
+    lib.fv_encode_batch.argtypes = [vp, vp, vp, i32, vp, i32, u32, vp]
+    lib.fv_kernel_timing.argtypes = [i32]
+    lib.fv_kernel_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.fv_strerror.argtypes = [i32]
+    lib.fv_strerror.restype = ctypes.c_char_p
+    lib.fv_last_device_error.argtypes = []
+    for f in (lib.fv_gmm_load, lib.fv_gmm_free, lib.fv_gmm_info, lib.fv_encode,
+              lib.fv_encode_batch, lib.fv_kernel_timing, lib.fv_kernel_timing_read,
+              lib.fv_last_device_error):
+        f.restype = i32
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().fv_strerror(int(code)).decode()
+
+
+def last_device_error() -> int:
+    return int(load().fv_last_device_error())
+
+
+def limits():
+    k, d = ctypes.c_int(), ctypes.c_int()
+    load().fv_limits(ctypes.byref(k), ctypes.byref(d))
+    return k.value, d.value
+
+
+def kernel_timing(enable: bool):
+    """Start (and reset) or stop event timing of libfv's kernel launches."""
+    _check(load().fv_kernel_timing(1 if enable else 0), "fv_kernel_timing")
+
+
+def kernel_timing_read(which: int = 0):
+    """(total_ms, launches) of kernel class `which` (0 statistics, 1 finalize) since reset."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(load().fv_kernel_timing_read(int(which), ctypes.byref(ms), ctypes.byref(n)),
+           "fv_kernel_timing_read")
+    return ms.value, n.value
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise FvError(rc, what)
+
+
+class Gmm:
+    """Owning wrapper of an ``fv_gmm*`` handle."""
+
+    def __init__(self, handle: int, K: int, D: int, device: int):
+        self.handle, self.K, self.D, self.device = handle, K, D, device
+
+    @property
+    def out_len(self) -> int:
+        return 2 * self.K * self.D
+
+    def free(self):
+        if self.handle:
+            _check(load().fv_gmm_free(ctypes.c_void_p(self.handle)), "fv_gmm_free")
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.fv_gmm_free(ctypes.c_void_p(self.handle))
+                self.handle = 0
+        except Exception:
+            pass
+
+
+def _host_f32(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def gmm_load(weights, means, variances, device: int = 0) -> Gmm:
+    mu = _host_f32(means)
+    if mu.ndim != 2:
+        raise ValueError("means must be [K, D]")
+    K, D = mu.shape
+    w = _host_f32(weights, (K,))
+    var = _host_f32(variances, (K, D))
+    h = ctypes.c_void_p()
+    rc = load().fv_gmm_load(K, D, w.ctypes.data, mu.ctypes.data, var.ctypes.data, int(device),
+                            ctypes.byref(h))
+    _check(rc, "fv_gmm_load")
+    return Gmm(h.value, K, D, int(device))
+
+
+def gmm_free(g: Gmm):
+    g.free()
+
+
+def gmm_info(g: Gmm):
+    K, D, dev = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().fv_gmm_info(ctypes.c_void_p(g.handle), ctypes.byref(K), ctypes.byref(D),
+                              ctypes.byref(dev)), "fv_gmm_info")
+    return K.value, D.value, dev.value
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.split(".")[0] == "torch"
+
+
+def _stream_handle(stream, device: int):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream(device).cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _marshal_x(g: Gmm, X):
+    """Returns (pointer, rows, is_device, keepalive)."""
+    if _is_torch(X):
+        import torch
+        if X.dtype != torch.float32 or X.dim() != 2 or X.shape[1] != g.D:
+            raise ValueError("X must be a float32 [N, D] tensor")
+        if not X.is_contiguous():
+            raise ValueError("X must be contiguous")
+        if X.is_cuda:
+            if X.device.index != g.device:
+                raise ValueError("X is on another device than the GMM")
+            return X.data_ptr(), X.shape[0], True, X
+        Xc = X.numpy()
+        return Xc.ctypes.data, Xc.shape[0], False, Xc
+    Xn = _host_f32(X)
+    if Xn.ndim != 2 or Xn.shape[1] != g.D:
+        raise ValueError("X must be [N, D]")
+    return Xn.ctypes.data, Xn.shape[0], False, Xn
+
+
+def _marshal_out(g: Gmm, out, n_vec: int, x_is_device: bool):
+    shape = (g.out_len,) if n_vec is None else (n_vec, g.out_len)
+    if out is None:
+        if x_is_device:
+            import torch
+            out = torch.empty(shape, dtype=torch.float32, device=f"cuda:{g.device}")
+        else:
+            out = np.empty(shape, dtype=np.float32)
+    if _is_torch(out):
+        import torch
+        if out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float32 tensor of shape {shape}")
+        if out.is_cuda:
+            return out, out.data_ptr(), True
+        return out, out.numpy().ctypes.data, False
+    if not isinstance(out, np.ndarray) or out.dtype != np.float32 or out.shape != shape \
+            or not out.flags.c_contiguous:
+        raise ValueError(f"out must be a contiguous float32 array of shape {shape}")
+    return out, out.ctypes.data, False
+
+
+def encode(g: Gmm, X, out=None, precision: int = PREC_FP32, flags: int = 0, stream=None):
+    """Fisher vector of one frame (fv_encode).  Returns `out` ([2KD] float32)."""
+    xp, n, xdev, _keep = _marshal_x(g, X)
+    out, op, odev = _marshal_out(g, out, None, xdev)
+    f = int(flags) & ~(X_DEVICE | OUT_DEVICE)
+    f |= (X_DEVICE if xdev else 0) | (OUT_DEVICE if odev else 0)
+    s = _stream_handle(stream, g.device) if (xdev or odev or stream is not None) else 0
+    rc = load().fv_encode(ctypes.c_void_p(g.handle), ctypes.c_void_p(xp), int(n),
+                          ctypes.c_void_p(op), int(precision), f, ctypes.c_void_p(s))
+    _check(rc, "fv_encode")
+    return out
+
+
+def encode_batch(g: Gmm, X, offsets, out=None, precision: int = PREC_FP32, flags: int = 0,
+                 stream=None):
+    """Fisher vectors of B frames (fv_encode_batch); offsets is a host int64 array [B+1]."""
+    xp, n, xdev, _keep = _marshal_x(g, X)
+    if _is_torch(offsets):
+        offsets = offsets.cpu().numpy()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or off.size < 1:
+        raise ValueError("offsets must be a 1-D int64 array of B+1 entries")
+    B = off.size - 1
+    if B > 0 and off[-1] != n:
+        raise ValueError("offsets[-1] must equal the number of rows of X")
+    out, op, odev = _marshal_out(g, out, B, xdev)
+    f = int(flags) & ~(X_DEVICE | OUT_DEVICE)
+    f |= (X_DEVICE if xdev else 0) | (OUT_DEVICE if odev else 0)
+    s = _stream_handle(stream, g.device) if (xdev or odev or stream is not None) else 0
+    rc = load().fv_encode_batch(ctypes.c_void_p(g.handle), ctypes.c_void_p(xp),
+                                ctypes.c_void_p(off.ctypes.data), int(B), ctypes.c_void_p(op),
+                                int(precision), f, ctypes.c_void_p(s))
+    _check(rc, "fv_encode_batch")
+    return out

@@ -1,0 +1,150 @@
+"""HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Gate (FP32): E_inf <= 1e-5 and E_2 <= 1e-5 (oracle.metrics); for the un-normalised forms the
+relative max-norm and 2-norm errors are gated at 1e-5 as well.  E_1 (strict per entry) is
+printed, not gated.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import fvsynth
+import oracle
+from oracle.metrics import errors, raw_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1604_03498_amd as fvmod
+    fvmod.load()
+    return fvmod
+
+
+def _gmm(fvmod, g):
+    return fvmod.gmm_load(g.weights, g.means, g.variances, device=0)
+
+
+def _check(name, got, ref, tol=TOL_FP32):
+    e = errors(got, ref)
+    say(f"  {name}: e_inf={e['e_inf']:.3e} e_2={e['e_2']:.3e} e_1={e['e_1']:.3e}")
+    assert np.all(np.isfinite(got)), name
+    assert e["e_inf"] <= tol and e["e_2"] <= tol, (name, e)
+
+
+CASES = [
+    # (name, K, D, N, gmm_seed, frame_seed, outliers)
+    ("k64_d64_n2000", 64, 64, 2000, 0, 0, 0.0),
+    ("k256_d64_n8000_outliers", 256, 64, 8000, 0, 100, 0.05),
+    ("k5_d3_n37_padded", 5, 3, 37, 1, 2, 0.05),
+    ("k33_d17_n1000_ragged", 33, 17, 1000, 2, 3, 0.05),
+    ("k200_d80_n3001", 200, 80, 3001, 3, 4, 0.05),
+    ("k256_d96_n513", 256, 96, 513, 4, 5, 0.05),
+    ("k1_d8_n100", 1, 8, 100, 5, 6, 0.0),
+    ("k128_d48_n1", 128, 48, 1, 6, 7, 0.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_fp32_encode_matches_oracle(fv, case):
+    import torch
+    name, K, D, N, gs, fs, out_frac = case
+    say(f"[gpu] fp32 encode {name}")
+    g = fvsynth.gmm(K, D, gs)
+    X = fvsynth.frame(g, N, fs, out_frac)
+    ref = oracle.encode_gmm(X, g)
+    h = _gmm(fv, g)
+    Xd = torch.from_numpy(X).cuda()
+    got = fv.encode(h, Xd).cpu().numpy()
+    torch.cuda.synchronize()
+    _check(name, got, ref)
+    # host pointers for X and out give the same result
+    got_h = fv.encode(h, X)
+    assert np.array_equal(got_h, got)
+
+
+@pytest.mark.parametrize("flags", [1, 2, 3])
+def test_fp32_unnormalised_forms(fv, flags):
+    import torch
+    say(f"[gpu] fp32 flags {flags}")
+    g = fvsynth.gmm(256, 64, 0)
+    X = fvsynth.frame(g, 4000, 11, 0.05)
+    ref = oracle.encode_gmm(X, g, flags=flags)
+    h = _gmm(fv, g)
+    cflags = (fv.NO_POWER_NORM if flags & 1 else 0) | (fv.NO_L2_NORM if flags & 2 else 0)
+    got = fv.encode(h, torch.from_numpy(X).cuda(), flags=cflags).cpu().numpy()
+    if flags == 3:
+        e = raw_errors(got, ref)
+        say(f"  raw: {e}")
+        assert e["rel_inf"] <= TOL_FP32 and e["rel_2"] <= TOL_FP32
+    else:
+        e = errors(got, ref, normalise=(flags == 2))
+        say(f"  {e}")
+        assert e["e_inf"] <= TOL_FP32 and e["e_2"] <= TOL_FP32
+
+
+def test_empty_frame_gives_zeros(fv):
+    say("[gpu] empty frame")
+    g = fvsynth.gmm(16, 8, 0)
+    h = _gmm(fv, g)
+    out = fv.encode(h, np.zeros((0, 8), np.float32))
+    assert out.shape == (256,) and np.all(out == 0)
+
+
+def test_batch_matches_oracle_and_is_frame_relative(fv):
+    import torch
+    say("[gpu] batch")
+    g = fvsynth.gmm(256, 64, 0)
+    sizes = [2500, 0, 1, 1100, 33, 4096]
+    X, off = fvsynth.batch_frames(g, sizes, seed0=300)
+    ref = oracle.encode_batch(X, off, g.weights, g.means, g.variances, nthreads=4)
+    h = _gmm(fv, g)
+    Xd = torch.from_numpy(X).cuda()
+    got = fv.encode_batch(h, Xd, off).cpu().numpy()
+    for b in range(len(sizes)):
+        if sizes[b] == 0:
+            assert np.all(got[b] == 0)
+        else:
+            _check(f"frame{b}(N={sizes[b]})", got[b], ref[b])
+    # the same frame inside a different batch is bitwise identical (frame-relative chunks)
+    X2, off2 = fvsynth.batch_frames(g, [77, 2500], seed0=299)
+    assert np.array_equal(X2[77:], X[:2500])
+    got2 = fv.encode_batch(h, torch.from_numpy(X2).cuda(), off2).cpu().numpy()
+    assert np.array_equal(got2[1], got[0])
+
+
+def test_batch_host_pointers_and_unnormalised(fv):
+    say("[gpu] batch host")
+    g = fvsynth.gmm(64, 32, 9)
+    X, off = fvsynth.batch_frames(g, [300, 2000, 45], seed0=7)
+    ref = oracle.encode_batch(X, off, g.weights, g.means, g.variances, flags=3)
+    h = _gmm(fv, g)
+    got = fv.encode_batch(h, X, off, flags=fv.NO_POWER_NORM | fv.NO_L2_NORM)
+    for b in range(3):
+        e = raw_errors(got[b], ref[b])
+        assert e["rel_inf"] <= TOL_FP32 and e["rel_2"] <= TOL_FP32, e
+
+
+def test_invalid_batch_offsets(fv):
+    g = fvsynth.gmm(8, 4, 0)
+    h = _gmm(fv, g)
+    X = np.zeros((10, 4), np.float32)
+    import ctypes
+    lib = fv.load()
+    out = np.zeros((2, 64), np.float32)
+    for off in ([1, 5, 10], [0, 6, 5]):
+        o = np.array(off, np.int64)
+        rc = lib.fv_encode_batch(ctypes.c_void_p(h.handle), X.ctypes.data, o.ctypes.data, 2,
+                                 out.ctypes.data, 0, 0, None)
+        assert rc == fv.E_INVAL
