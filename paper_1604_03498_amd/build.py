@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfv.so")
 
-SOURCES = ["fv_api.cpp", "fv_kernels.hip"]
+SOURCES = ["fv_api.cpp", "fv_kernels.hip", "fv_split.hip", "fv_finalize.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -33,20 +33,22 @@ def hipcc_flags():
 
 def build(verbose: bool = False) -> str:
     with tempfile.TemporaryDirectory(prefix="fvbuild_") as td:
-        objs = []
-        for src in SOURCES:
-            obj = os.path.join(td, src + ".o")
-            cmd = [HIPCC] + hipcc_flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        objs = [os.path.join(td, src + ".o") for src in SOURCES]
+        cmds = [[HIPCC] + hipcc_flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+                for src, obj in zip(SOURCES, objs)]
+        procs = []
+        for cmd in cmds:
             if verbose:
                 print(" ".join(cmd), flush=True)
-            r = subprocess.run(cmd, capture_output=True, text=True)
-            msgs = [ln for ln in (r.stderr or "").splitlines()
+            procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
+        for src, p in zip(SOURCES, procs):
+            _, err = p.communicate()
+            msgs = [ln for ln in (err or "").splitlines()
                     if "packed-fp32-ops" not in ln and "unknown target feature" not in ln]
-            if r.returncode != 0:
+            if p.returncode != 0:
                 raise RuntimeError(f"hipcc failed on {src}:\n" + "\n".join(msgs))
             if verbose and msgs:
                 print("\n".join(msgs))
-            objs.append(obj)
         tmp_lib = os.path.join(td, "libfv.so")
         cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp_lib]
         r = subprocess.run(cmd, capture_output=True, text=True)

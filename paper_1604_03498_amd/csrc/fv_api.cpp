@@ -131,23 +131,63 @@ int ensure_pinned(Workspace* ws, size_t need) {
 
 bool finite_f(float v) { return std::isfinite(v); }
 
-// Chunk length for a single frame: enough items to give every CU work, in whole tiles.
-int single_frame_chunk(int64_t N, int device, int W) {
-  const int64_t target = (int64_t)device_cu_count(device) * std::max(1, 8 / W);
-  int64_t tiles = (N + fv::kTile - 1) / fv::kTile;
-  int64_t per = (tiles + target - 1) / target;
-  if (per < 1) per = 1;
-  const int64_t maxP = (int64_t)1 << 20;
-  int64_t P = per * fv::kTile;
-  return (int)std::min(P, maxP);
+enum class Path { kFused, kSplit };
+
+// Path override for tests and measurements: FV_PATH=fused|split (default: automatic).
+int path_override() {
+  const char* e = std::getenv("FV_PATH");
+  if (!e) return 0;
+  if (std::strcmp(e, "fused") == 0) return 1;
+  if (std::strcmp(e, "split") == 0) return 2;
+  return 0;
 }
 
+// Workgroups of the fused kernel (or of the first pass) that fit on the device at once:
+// one 8-wave workgroup per CU at 256 components (register bound), more for fewer waves.
+int resident_fused(int device, int Wg) { return device_cu_count(device) * std::max(1, 8 / Wg); }
+
+// Single frame: the fused kernel needs several 32-row tiles per resident workgroup to amortise
+// its per-chunk partial write; below that the two-pass path (more, smaller workgroups and
+// fewer partial slots) is used.  More than 256 components always take the two-pass path.
+Path choose_single(const fv::Consts& c, int64_t N, int device) {
+  if (c.Kp > fv::kFusedMaxK) return Path::kSplit;
+  const int o = path_override();
+  if (o == 1) return Path::kFused;
+  if (o == 2) return Path::kSplit;
+  return N < (int64_t)4 * fv::kTile * resident_fused(device, c.Wg) ? Path::kSplit : Path::kFused;
+}
+
+Path choose_batch(const fv::Consts& c) {
+  if (c.Kp > fv::kFusedMaxK) return Path::kSplit;
+  return path_override() == 2 ? Path::kSplit : Path::kFused;
+}
+
+// Chunk length of the fused kernel for a single frame: enough items to give every resident
+// workgroup work, in whole tiles.
+int fused_single_chunk(int64_t N, int device, int Wg) {
+  const int64_t target = resident_fused(device, Wg);
+  const int64_t tiles = (N + fv::kTile - 1) / fv::kTile;
+  const int64_t per = std::max<int64_t>(1, (tiles + target - 1) / target);
+  return (int)std::min<int64_t>(per * fv::kTile, (int64_t)1 << 20);
+}
+
+// Chunk length of the second pass for a single frame: about two workgroups per CU over all
+// (chunk, slice) pairs, in whole rounds of the workgroup's four 32-row tiles.
+int split_single_chunk(int64_t N, int device, int slices) {
+  const int round = fv::sliced_rows_per_wave_round();
+  const int64_t target_chunks = std::max<int64_t>(1, (2 * device_cu_count(device) + slices - 1) / slices);
+  const int64_t per = (N + target_chunks - 1) / target_chunks;
+  const int64_t P = std::max<int64_t>(round, (per + round - 1) / round * round);
+  return (int)std::min<int64_t>(P, (int64_t)1 << 20);
+}
+
+// Frame-relative chunk length of the batched path (a multiple of 128 rows).
 int batch_chunk() {
   static int P = [] {
     int v = 1024;
     if (const char* e = std::getenv("FV_BATCH_CHUNK")) {
       int x = std::atoi(e);
-      if (x >= fv::kTile) v = (x / fv::kTile) * fv::kTile;
+      if (x >= 128) v = (x / 128) * 128;
     }
     return v;
   }();
@@ -284,9 +324,15 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
   fv::Consts c{};
   c.K = K;
   c.D = D;
-  c.W = 1;
-  while (c.W * fv::kCompsPerWave < K) c.W *= 2;
-  c.Kp = c.W * fv::kCompsPerWave;
+  if (K <= fv::kFusedMaxK) {
+    c.Wg = 1;
+    while (c.Wg * fv::kCompsPerWave < K) c.Wg *= 2;
+    c.Kp = c.Wg * fv::kCompsPerWave;
+  } else {
+    c.Wg = fv::kMaxWaves;
+    const int grp = fv::kMaxWaves * fv::kCompsPerWave;
+    c.Kp = (K + grp - 1) / grp * grp;
+  }
   c.DP = ((D + 15) / 16) * 16;
   const int Kp = c.Kp, DP = c.DP;
 
@@ -410,37 +456,59 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   if (!ws) return FV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ws->mu);
 
-  const int P = N > 0 ? single_frame_chunk(N, gmm->device, c.W) : fv::kTile;
-  const int64_t n_items64 = N > 0 ? (N + P - 1) / P : 0;
-  const int n_items = (int)n_items64;
+  const Path path = choose_single(c, N, gmm->device);
+  const int slices = c.Kp / fv::kCompsPerWave;
+  int P = fv::kTile;
+  if (N > 0)
+    P = (path == Path::kFused) ? fused_single_chunk(N, gmm->device, c.Wg)
+                               : split_single_chunk(N, gmm->device, slices);
+  const int n_items = N > 0 ? (int)((N + P - 1) / P) : 0;
+  const int n_groups = (n_items + fv::kGroupItems - 1) / fv::kGroupItems;
+  const int G = fv::lse_groups(c);
   const int nblk = fv::finalize_blocks(c);
   const size_t out_len = (size_t)2 * c.K * c.D;
   const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
+  const size_t b_grp = align256((size_t)n_groups * fv::slot_floats(c) * 8);
   const size_t b_norm = align256((size_t)nblk * 8);
+  const size_t b_lse = (path == Path::kSplit) ? align256((size_t)G * N * 8) : 0;
   const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)N * c.D * 4);
   const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256(out_len * 4);
-  int rc = ensure_dev(ws, b_part + b_norm + b_x + b_out, s);
+  int rc = ensure_dev(ws, b_part + b_grp + b_norm + b_lse + b_x + b_out, s);
   if (rc) return rc;
-  float* partials = reinterpret_cast<float*>(ws->dev);
-  double* normpart = reinterpret_cast<double*>(ws->dev + b_part);
-  float* xdev = reinterpret_cast<float*>(ws->dev + b_part + b_norm);
-  float* odev = reinterpret_cast<float*>(ws->dev + b_part + b_norm + b_x);
+  char* base = ws->dev;
+  float* partials = reinterpret_cast<float*>(base);
+  double* gbuf = reinterpret_cast<double*>(base + b_part);
+  double* normpart = reinterpret_cast<double*>(base + b_part + b_grp);
+  float2* lse = reinterpret_cast<float2*>(base + b_part + b_grp + b_norm);
+  float* xdev = reinterpret_cast<float*>(base + b_part + b_grp + b_norm + b_lse);
+  float* odev = reinterpret_cast<float*>(base + b_part + b_grp + b_norm + b_lse + b_x);
 
   const float* Xd = X;
   if (!(flags & FV_X_DEVICE) && N > 0) {
     FV_HIP(hipMemcpyAsync(xdev, X, (size_t)N * c.D * 4, hipMemcpyHostToDevice, s));
     Xd = xdev;
   }
+  if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
   float* Od = (flags & FV_OUT_DEVICE) ? out : odev;
   const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
-  if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
 
-  hipEvent_t t0 = n_items > 0 ? timing_begin(s) : nullptr;
-  FV_HIP(fv::launch_stats(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
-  timing_end(t0, 0, s);
-  fv::Frame single{N, 0, n_items};
+  if (n_items > 0) {
+    hipEvent_t t0 = timing_begin(s);
+    if (path == Path::kFused) {
+      FV_HIP(fv::launch_stats(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
+    } else {
+      const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
+      const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
+      FV_HIP(fv::launch_lse(c, precision, Xd, vec_ok, N, nullptr, n_tiles, grid1, lse, N, s));
+      FV_HIP(fv::launch_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, lse, N,
+                               partials, s));
+    }
+    timing_end(t0, 0, s);
+  }
+  fv::Frame single{N, 0, n_items, 0, n_groups};
   hipEvent_t t1 = timing_begin(s);
-  FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, flags, Od, normpart, s));
+  FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, nullptr, n_groups, flags, Od, gbuf,
+                             normpart, s));
   timing_end(t1, 1, s);
   if (!(flags & FV_OUT_DEVICE))
     FV_HIP(hipMemcpyAsync(out, Od, out_len * 4, hipMemcpyDeviceToHost, s));
@@ -464,17 +532,21 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   if (rows > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
 
   // Frame-relative chunking: frame b's chunk j covers its rows [j*P, (j+1)*P).
+  const Path path = choose_batch(c);
   const int P = batch_chunk();
   std::vector<fv::Frame> frames((size_t)B);
-  int64_t n_items64 = 0;
+  int64_t n_items64 = 0, n_groups64 = 0;
   for (int b = 0; b < B; ++b) {
     const int64_t n = offsets[b + 1] - offsets[b];
     const int64_t ni = (n + P - 1) / P;
-    frames[b] = fv::Frame{n, (int32_t)n_items64, (int32_t)ni};
+    const int64_t ng = (ni + fv::kGroupItems - 1) / fv::kGroupItems;
+    frames[b] = fv::Frame{n, (int32_t)n_items64, (int32_t)ni, (int32_t)n_groups64, (int32_t)ng};
     n_items64 += ni;
+    n_groups64 += ng;
   }
   if (n_items64 > (int64_t)1 << 30) return FV_E_UNSUPPORTED;
   const int n_items = (int)n_items64;
+  const int n_groups = (int)n_groups64;
 
   DeviceGuard g(gmm->device);
   if (g.status() != hipSuccess) return hip_fail(g.status());
@@ -483,40 +555,56 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   if (!ws) return FV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ws->mu);
 
+  const int G = fv::lse_groups(c);
   const int nblk = fv::finalize_blocks(c);
   const size_t out_len = (size_t)2 * c.K * c.D;
   const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
+  const size_t b_grp = align256((size_t)n_groups * fv::slot_floats(c) * 8);
   const size_t b_norm = align256((size_t)B * nblk * 8);
+  const size_t b_lse = (path == Path::kSplit) ? align256((size_t)G * rows * 8) : 0;
   const size_t b_frames = align256((size_t)B * sizeof(fv::Frame));
   const size_t b_items = align256((size_t)n_items * sizeof(fv::Item));
+  const size_t b_groups = align256((size_t)n_groups * sizeof(fv::Group));
+  const size_t b_tab = b_frames + b_items + b_groups;
   const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)rows * c.D * 4);
   const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256((size_t)B * out_len * 4);
-  int rc = ensure_dev(ws, b_part + b_norm + b_frames + b_items + b_x + b_out, s);
+  int rc = ensure_dev(ws, b_part + b_grp + b_norm + b_lse + b_tab + b_x + b_out, s);
   if (rc) return rc;
-  rc = ensure_pinned(ws, b_frames + b_items);
+  rc = ensure_pinned(ws, b_tab);
   if (rc) return rc;
   char* base = ws->dev;
   float* partials = reinterpret_cast<float*>(base);
-  double* normpart = reinterpret_cast<double*>(base + b_part);
-  fv::Frame* dframes = reinterpret_cast<fv::Frame*>(base + b_part + b_norm);
-  fv::Item* ditems = reinterpret_cast<fv::Item*>(base + b_part + b_norm + b_frames);
-  float* xdev = reinterpret_cast<float*>(base + b_part + b_norm + b_frames + b_items);
-  float* odev = reinterpret_cast<float*>(base + b_part + b_norm + b_frames + b_items + b_x);
+  double* gbuf = reinterpret_cast<double*>(base + b_part);
+  double* normpart = reinterpret_cast<double*>(base + b_part + b_grp);
+  float2* lse = reinterpret_cast<float2*>(base + b_part + b_grp + b_norm);
+  char* tab = base + b_part + b_grp + b_norm + b_lse;
+  fv::Frame* dframes = reinterpret_cast<fv::Frame*>(tab);
+  fv::Item* ditems = reinterpret_cast<fv::Item*>(tab + b_frames);
+  fv::Group* dgroups = reinterpret_cast<fv::Group*>(tab + b_frames + b_items);
+  float* xdev = reinterpret_cast<float*>(tab + b_tab);
+  float* odev = reinterpret_cast<float*>(tab + b_tab + b_x);
 
-  // work table in pinned memory, then one H2D copy
+  // work tables in pinned memory (same layout as on the device), then one H2D copy
   fv::Frame* hframes = reinterpret_cast<fv::Frame*>(ws->pinned);
   fv::Item* hitems = reinterpret_cast<fv::Item*>(ws->pinned + b_frames);
+  fv::Group* hgroups = reinterpret_cast<fv::Group*>(ws->pinned + b_frames + b_items);
   std::memcpy(hframes, frames.data(), (size_t)B * sizeof(fv::Frame));
   {
-    int64_t i = 0;
-    for (int b = 0; b < B; ++b)
+    int64_t i = 0, gi = 0;
+    for (int b = 0; b < B; ++b) {
       for (int32_t q = 0; q < frames[b].nitems; ++q, ++i) {
         const int64_t r0 = (int64_t)q * P;
         const int64_t nr = std::min<int64_t>(P, frames[b].nrows - r0);
         hitems[i] = fv::Item{offsets[b] + r0, (int32_t)nr, 0};
       }
+      for (int32_t q = 0; q < frames[b].ngroups; ++q, ++gi) {
+        const int32_t i0 = frames[b].item0 + q * fv::kGroupItems;
+        const int32_t ni = std::min<int32_t>(fv::kGroupItems, frames[b].item0 + frames[b].nitems - i0);
+        hgroups[gi] = fv::Group{i0, ni};
+      }
+    }
   }
-  FV_HIP(hipMemcpyAsync(dframes, ws->pinned, b_frames + b_items, hipMemcpyHostToDevice, s));
+  FV_HIP(hipMemcpyAsync(dframes, ws->pinned, b_tab, hipMemcpyHostToDevice, s));
   FV_HIP(hipEventRecord(ws->pin_done, s));
   ws->pin_pending = true;
 
@@ -528,13 +616,25 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
   float* Od = (flags & FV_OUT_DEVICE) ? out : odev;
   const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
-  const int resident = device_cu_count(gmm->device) * std::max(1, 8 / c.W);
-  const int grid = std::max(1, std::min(n_items, resident));
-  hipEvent_t t0 = n_items > 0 ? timing_begin(s) : nullptr;
-  FV_HIP(fv::launch_stats(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid, partials, s));
-  timing_end(t0, 0, s);
+  if (n_items > 0) {
+    hipEvent_t t0 = timing_begin(s);
+    if (path == Path::kFused) {
+      const int grid = std::max(1, std::min(n_items, resident_fused(gmm->device, c.Wg)));
+      FV_HIP(fv::launch_stats(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid, partials, s));
+    } else {
+      const int n_tiles = (int)((rows + fv::kTile - 1) / fv::kTile);
+      const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
+      FV_HIP(fv::launch_lse(c, precision, Xd, vec_ok, rows, nullptr, n_tiles, grid1, lse, rows, s));
+      const int slices = c.Kp / fv::kCompsPerWave;
+      const int grid2 = std::max(1, std::min(n_items, 2 * device_cu_count(gmm->device) / slices + 1));
+      FV_HIP(fv::launch_sliced(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid2, lse, rows,
+                               partials, s));
+    }
+    timing_end(t0, 0, s);
+  }
   hipEvent_t t1 = timing_begin(s);
-  FV_HIP(fv::launch_finalize(c, partials, dframes, fv::Frame{0, 0, 0}, B, flags, Od, normpart, s));
+  FV_HIP(fv::launch_finalize(c, partials, dframes, fv::Frame{0, 0, 0, 0, 0}, B, dgroups, n_groups,
+                             flags, Od, gbuf, normpart, s));
   timing_end(t1, 1, s);
   if (!(flags & FV_OUT_DEVICE))
     FV_HIP(hipMemcpyAsync(out, Od, (size_t)B * out_len * 4, hipMemcpyDeviceToHost, s));

@@ -10,14 +10,16 @@ namespace fv {
 constexpr int kTile = 32;        // descriptors per tile (one 32x32 MFMA block of rows)
 constexpr int kCompsPerWave = 32; // GMM components owned by one wavefront
 constexpr int kMaxWaves = 8;      // 8 waves x 32 components = 256 components per workgroup
-constexpr int kMaxK = kCompsPerWave * kMaxWaves;
+constexpr int kFusedMaxK = kCompsPerWave * kMaxWaves;  // fused single-pass kernel
+constexpr int kMaxK = 1024;                               // two-pass path
 constexpr int kMaxD = 96;
 
 // Device-resident constants of one GMM (all pointers are device memory owned by the handle).
 struct Consts {
   int K, D;    // real sizes
-  int Kp, DP;  // padded: Kp = 32 * W, DP = D rounded up to a multiple of 16
-  int W;       // waves per workgroup (1, 2, 4 or 8)
+  int Kp, DP;  // padded: Kp = 32 * Wg * groups, DP = D rounded up to a multiple of 16
+  int Wg;      // waves per component group (1, 2, 4 or 8); one group when Kp <= 256, else
+               // groups of 256 components (Wg = 8)
   // E-step operand, log2(e)-scaled, [2*DP][Kp] f32: rows 0..DP-1 multiply x, rows DP..2DP-1
   // multiply x^2; padded rows and columns are zero.
   const float* A32;
@@ -43,14 +45,27 @@ struct Item {
   int32_t pad;
 };
 
-// One frame for the finalize step: its descriptor count and its partial slots.
+// One frame for the finalize step: its descriptor count, its partial slots (items) and its
+// chunk groups (consecutive runs of at most kGroupItems slots reduced together).
 struct Frame {
   int64_t nrows;
   int32_t item0;
   int32_t nitems;
+  int32_t group0;
+  int32_t ngroups;
 };
 
+// A chunk group: slots [item0, item0 + nitems) are summed (double, in index order) into one
+// row of the group buffer.
+struct Group {
+  int32_t item0;
+  int32_t nitems;
+};
+
+constexpr int kGroupItems = 16;
+
 inline size_t slot_floats(const Consts& c) { return (size_t)(2 * c.DP + 1) * c.Kp; }
+inline int lse_groups(const Consts& c) { return c.Kp / (kCompsPerWave * c.Wg); }
 
 // Statistics kernel: for every item, the raw moments S0 = sum gamma, S1 = gamma^T X,
 // S2 = gamma^T X^2 of its rows go to partials[item] laid out [2*DP+1][Kp] (rows: x features,
@@ -60,14 +75,33 @@ hipError_t launch_stats(const Consts& c, int precision, const float* X, bool vec
                         int P, const Item* items, int n_items, int grid, float* partials,
                         hipStream_t stream);
 
-// Finalize: per frame, sum its partial slots in order (double), form u and v, apply the
-// signed square root unless flagged off, write out[frame][2*K*D]; then L2-normalise unless
-// flagged off.  `frames` is a device table of B frames, or null with B == 1 and `single`.
-hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* frames,
-                           Frame single, int B, unsigned flags, float* out, double* normpart,
-                           hipStream_t stream);
+// First pass of the two-pass path: for every row and component group g, (max_k logit,
+// log2 sum_k 2^(logit - max)) over the group's components, written to lse[g * lse_stride +
+// row].  Items are tiles of 32 rows (`items` device table, or arithmetic over N when null).
+hipError_t launch_lse(const Consts& c, int precision, const float* X, bool vec_ok, int64_t N,
+                      const Item* items, int n_items, int grid, float2* lse, int64_t lse_stride,
+                      hipStream_t stream);
 
-// Blocks per frame used by launch_finalize (size of normpart per frame).
+// Second pass: statistics per (item, 32-component slice) from the first pass's normalisers,
+// written to the item's partial slot (same layout as launch_stats).  Items hold chunks of P
+// rows (table or arithmetic); grid = (grid, Kp / 32) workgroups.
+hipError_t launch_sliced(const Consts& c, int precision, const float* X, bool vec_ok, int64_t N,
+                         int P, const Item* items, int n_items, int grid, const float2* lse,
+                         int64_t lse_stride, float* partials, hipStream_t stream);
+
+// Rows one workgroup of the second pass consumes per round (4 waves x 32-row tiles).
+int sliced_rows_per_wave_round();
+
+// Finalize: (1) every chunk group's slots are summed in index order in double precision into
+// gbuf[group]; (2) per frame, the group sums are added in order, turned into u and v, signed-
+// square-rooted unless flagged off, and written to out[frame][2*K*D]; (3) L2 normalisation
+// unless flagged off.  `frames` / `groups` are device tables, or null for one frame (B == 1,
+// `single`, groups of kGroupItems consecutive slots).
+hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* frames,
+                           Frame single, int B, const Group* groups, int n_groups, unsigned flags,
+                           float* out, double* gbuf, double* normpart, hipStream_t stream);
+
+// Blocks per frame of the assembly step (size of normpart per frame).
 int finalize_blocks(const Consts& c);
 
 }  // namespace fv

@@ -61,7 +61,7 @@ def test_gmm_load_validation():
         assert _load_raw(K, D, w, mu, v2)[0] == fv.E_INVAL
     m2 = mu.copy(); m2[0, 0] = np.nan
     assert _load_raw(K, D, w, m2, var)[0] == fv.E_INVAL
-    big = 1024
+    big = 2048
     assert _load_raw(big, D, np.full(big, 1 / big, np.float32), np.zeros((big, D), np.float32),
                      np.ones((big, D), np.float32))[0] == fv.E_UNSUPPORTED
     assert fv.load().fv_gmm_load(K, D, w.ctypes.data, mu.ctypes.data, var.ctypes.data, 0, None) \

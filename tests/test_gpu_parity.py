@@ -56,11 +56,17 @@ CASES = [
 ]
 
 
+@pytest.fixture(params=["fused", "split"])
+def path(request, monkeypatch):
+    monkeypatch.setenv("FV_PATH", request.param)
+    return request.param
+
+
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_fp32_encode_matches_oracle(fv, case):
+def test_fp32_encode_matches_oracle(fv, case, path):
     import torch
     name, K, D, N, gs, fs, out_frac = case
-    say(f"[gpu] fp32 encode {name}")
+    say(f"[gpu] fp32 encode {name} path={path}")
     g = fvsynth.gmm(K, D, gs)
     X = fvsynth.frame(g, N, fs, out_frac)
     ref = oracle.encode_gmm(X, g)
@@ -102,9 +108,37 @@ def test_empty_frame_gives_zeros(fv):
     assert out.shape == (256,) and np.all(out == 0)
 
 
-def test_batch_matches_oracle_and_is_frame_relative(fv):
+def test_large_k_two_pass(fv):
+    """More than 256 components (two component groups in the first pass)."""
     import torch
-    say("[gpu] batch")
+    for K, D, N in ((512, 80, 6000), (300, 64, 777)):
+        say(f"[gpu] fp32 two-pass K={K} D={D} N={N}")
+        g = fvsynth.gmm(K, D, 0)
+        X = fvsynth.frame(g, N, 12, 0.05)
+        ref = oracle.encode_gmm(X, g)
+        h = _gmm(fv, g)
+        got = fv.encode(h, torch.from_numpy(X).cuda()).cpu().numpy()
+        _check(f"K{K}_D{D}", got, ref)
+
+
+def test_paths_agree(fv, monkeypatch):
+    import torch
+    say("[gpu] fused vs split")
+    g = fvsynth.gmm(256, 64, 0)
+    X = torch.from_numpy(fvsynth.frame(g, 8000, 100, 0.05)).cuda()
+    h = _gmm(fv, g)
+    monkeypatch.setenv("FV_PATH", "fused")
+    a = fv.encode(h, X).cpu().numpy()
+    monkeypatch.setenv("FV_PATH", "split")
+    b = fv.encode(h, X).cpu().numpy()
+    e = errors(a, b)
+    say(f"  fused vs split: {e}")
+    assert e["e_inf"] <= 5e-6 and e["e_2"] <= 5e-6
+
+
+def test_batch_matches_oracle_and_is_frame_relative(fv, path):
+    import torch
+    say(f"[gpu] batch path={path}")
     g = fvsynth.gmm(256, 64, 0)
     sizes = [2500, 0, 1, 1100, 33, 4096]
     X, off = fvsynth.batch_frames(g, sizes, seed0=300)
