@@ -131,6 +131,79 @@ int ensure_pinned(Workspace* ws, size_t need) {
 
 bool finite_f(float v) { return std::isfinite(v); }
 
+// Round-to-nearest-even conversions for the operand fragments (inputs are finite).
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_to_f32(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+uint16_t f16_bits(_Float16 h) {
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+
+// ---- precision dispatch of the statistics kernels
+fv::Frags16 frags(const fv::Consts& c, int precision) {
+  switch (precision) {
+    case FV_PREC_BF16_SPLIT: return fv::Frags16{c.Abf_hi, c.Abf_lo};
+    case FV_PREC_FP16_SPLIT: return fv::Frags16{c.Ah_hi, c.Ah_lo};
+    case FV_PREC_BF16: return fv::Frags16{c.Abf_hi, nullptr};
+    default: return fv::Frags16{nullptr, nullptr};
+  }
+}
+
+hipError_t run_stats(const fv::Consts& c, int prec, const float* X, bool vec_ok, int64_t N, int P,
+                     const fv::Item* items, int n_items, int grid, float* partials, hipStream_t s) {
+  const fv::Frags16 fr = frags(c, prec);
+  switch (prec) {
+    case FV_PREC_FP32: return fv::launch_stats(c, 0, X, vec_ok, N, P, items, n_items, grid, partials, s);
+    case FV_PREC_BF16_SPLIT: return fv::launch_stats16_bf16s(c, fr, X, vec_ok, N, P, items, n_items, grid, partials, s);
+    case FV_PREC_FP16_SPLIT: return fv::launch_stats16_f16s(c, fr, X, vec_ok, N, P, items, n_items, grid, partials, s);
+    default: return fv::launch_stats16_bf16(c, fr, X, vec_ok, N, P, items, n_items, grid, partials, s);
+  }
+}
+
+hipError_t run_lse(const fv::Consts& c, int prec, const float* X, bool vec_ok, int64_t N,
+                   int n_tiles, int grid, float2* lse, int64_t stride, hipStream_t s) {
+  const fv::Frags16 fr = frags(c, prec);
+  switch (prec) {
+    case FV_PREC_FP32: return fv::launch_lse(c, 0, X, vec_ok, N, nullptr, n_tiles, grid, lse, stride, s);
+    case FV_PREC_BF16_SPLIT: return fv::launch_lse16_bf16s(c, fr, X, vec_ok, N, nullptr, n_tiles, grid, lse, stride, s);
+    case FV_PREC_FP16_SPLIT: return fv::launch_lse16_f16s(c, fr, X, vec_ok, N, nullptr, n_tiles, grid, lse, stride, s);
+    default: return fv::launch_lse16_bf16(c, fr, X, vec_ok, N, nullptr, n_tiles, grid, lse, stride, s);
+  }
+}
+
+hipError_t run_sliced(const fv::Consts& c, int prec, const float* X, bool vec_ok, int64_t N, int P,
+                      const fv::Item* items, int n_items, int grid, const float2* lse,
+                      int64_t stride, float* partials, hipStream_t s) {
+  const fv::Frags16 fr = frags(c, prec);
+  switch (prec) {
+    case FV_PREC_FP32: return fv::launch_sliced(c, 0, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
+    case FV_PREC_BF16_SPLIT: return fv::launch_sliced16_bf16s(c, fr, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
+    case FV_PREC_FP16_SPLIT: return fv::launch_sliced16_f16s(c, fr, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
+    default: return fv::launch_sliced16_bf16(c, fr, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
+  }
+}
+
+// Rows one second-pass workgroup consumes per round of its waves (32-row tiles).
+int sliced_round(const fv::Consts& c, int prec) {
+  switch (prec) {
+    case FV_PREC_FP32: return fv::sliced_rows_per_wave_round();
+    case FV_PREC_BF16_SPLIT: return fv::kTile * fv::sliced16_waves_bf16s(c.DP);
+    case FV_PREC_FP16_SPLIT: return fv::kTile * fv::sliced16_waves_f16s(c.DP);
+    default: return fv::kTile * fv::sliced16_waves_bf16(c.DP);
+  }
+}
+
 enum class Path { kFused, kSplit };
 
 // Path override for tests and measurements: FV_PATH=fused|split (default: automatic).
@@ -173,8 +246,7 @@ int fused_single_chunk(int64_t N, int device, int Wg) {
 
 // Chunk length of the second pass for a single frame: about two workgroups per CU over all
 // (chunk, slice) pairs, in whole rounds of the workgroup's four 32-row tiles.
-int split_single_chunk(int64_t N, int device, int slices) {
-  const int round = fv::sliced_rows_per_wave_round();
+int split_single_chunk(int64_t N, int device, int slices, int round) {
   const int64_t target_chunks = std::max<int64_t>(1, (2 * device_cu_count(device) + slices - 1) / slices);
   const int64_t per = (N + target_chunks - 1) / target_chunks;
   const int64_t P = std::max<int64_t>(round, (per + round - 1) / round * round);
@@ -340,7 +412,8 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
   // per-model constant the kernels need)
   const double LOG2E = 1.4426950408889634073599246810019;
   std::vector<float> A((size_t)2 * DP * Kp, 0.f), cc((size_t)Kp, -1e30f);
-  std::vector<uint16_t> abh(A.size(), 0), abl(A.size(), 0), ahh(A.size(), 0), ahl(A.size(), 0);
+  const size_t nfrag = (size_t)2 * DP * Kp;  // same element count as A, fragment order
+  std::vector<uint16_t> abh(nfrag, 0), abl(nfrag, 0), ahh(nfrag, 0), ahl(nfrag, 0);
   std::vector<double> mu64(KD), isd64(KD), ivar64(KD), cu64(K), cv64(K);
   for (int k = 0; k < K; ++k) {
     double logdet = 0.0, quad = 0.0;
@@ -362,7 +435,22 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
     cv64[k] = 1.0 / std::sqrt(2.0 * w);
   }
 
-  // ---- one device block: A32 | c32 | 4 x 16-bit splits (filled by the split forms) | doubles
+  // 16-bit hi/lo operand fragments: fragment (s, h, comp) = A[16s + 8h + e][comp], e = 0..7
+  for (int st = 0; st < 2 * DP / 16; ++st)
+    for (int hh = 0; hh < 2; ++hh)
+      for (int k = 0; k < Kp; ++k)
+        for (int e = 0; e < 8; ++e) {
+          const float v = A[(size_t)(16 * st + 8 * hh + e) * Kp + k];
+          const size_t o = (((size_t)st * 2 + hh) * Kp + k) * 8 + e;
+          const uint16_t bh = bf16_rne(v);
+          abh[o] = bh;
+          abl[o] = bf16_rne(v - bf16_to_f32(bh));
+          const _Float16 fh = (_Float16)v;
+          ahh[o] = f16_bits(fh);
+          ahl[o] = f16_bits((_Float16)(v - (float)fh));
+        }
+
+  // ---- one device block: A32 | c32 | 4 x 16-bit operand fragments | doubles
   const size_t nA = A.size();
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -371,7 +459,7 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
     return o;
   };
   const size_t oA = take(nA * 4), oc = take((size_t)Kp * 4);
-  const size_t oBH = take(nA * 2), oBL = take(nA * 2), oHH = take(nA * 2), oHL = take(nA * 2);
+  const size_t oBH = take(nfrag * 2), oBL = take(nfrag * 2), oHH = take(nfrag * 2), oHL = take(nfrag * 2);
   const size_t oMu = take(KD * 8), oIsd = take(KD * 8), oIvar = take(KD * 8);
   const size_t oCu = take((size_t)K * 8), oCv = take((size_t)K * 8);
   const size_t total = off;
@@ -385,10 +473,10 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
   std::vector<char> host(total, 0);
   std::memcpy(host.data() + oA, A.data(), nA * 4);
   std::memcpy(host.data() + oc, cc.data(), (size_t)Kp * 4);
-  std::memcpy(host.data() + oBH, abh.data(), nA * 2);
-  std::memcpy(host.data() + oBL, abl.data(), nA * 2);
-  std::memcpy(host.data() + oHH, ahh.data(), nA * 2);
-  std::memcpy(host.data() + oHL, ahl.data(), nA * 2);
+  std::memcpy(host.data() + oBH, abh.data(), nfrag * 2);
+  std::memcpy(host.data() + oBL, abl.data(), nfrag * 2);
+  std::memcpy(host.data() + oHH, ahh.data(), nfrag * 2);
+  std::memcpy(host.data() + oHL, ahl.data(), nfrag * 2);
   std::memcpy(host.data() + oMu, mu64.data(), KD * 8);
   std::memcpy(host.data() + oIsd, isd64.data(), KD * 8);
   std::memcpy(host.data() + oIvar, ivar64.data(), KD * 8);
@@ -446,7 +534,6 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   if (!gmm || !out || N < 0 || (N > 0 && !X)) return FV_E_INVAL;
   if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
   if (flags & ~kAllFlags) return FV_E_INVAL;
-  if (precision != FV_PREC_FP32) return FV_E_UNSUPPORTED;
   const fv::Consts& c = gmm->c;
   if (N > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
   DeviceGuard g(gmm->device);
@@ -461,7 +548,7 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   int P = fv::kTile;
   if (N > 0)
     P = (path == Path::kFused) ? fused_single_chunk(N, gmm->device, c.Wg)
-                               : split_single_chunk(N, gmm->device, slices);
+                               : split_single_chunk(N, gmm->device, slices, sliced_round(c, precision));
   const int n_items = N > 0 ? (int)((N + P - 1) / P) : 0;
   const int n_groups = (n_items + fv::kGroupItems - 1) / fv::kGroupItems;
   const int G = fv::lse_groups(c);
@@ -495,13 +582,12 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   if (n_items > 0) {
     hipEvent_t t0 = timing_begin(s);
     if (path == Path::kFused) {
-      FV_HIP(fv::launch_stats(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
+      FV_HIP(run_stats(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
     } else {
       const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
       const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
-      FV_HIP(fv::launch_lse(c, precision, Xd, vec_ok, N, nullptr, n_tiles, grid1, lse, N, s));
-      FV_HIP(fv::launch_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, lse, N,
-                               partials, s));
+      FV_HIP(run_lse(c, precision, Xd, vec_ok, N, n_tiles, grid1, lse, N, s));
+      FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, lse, N, partials, s));
     }
     timing_end(t0, 0, s);
   }
@@ -527,7 +613,6 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   if (B == 0) return FV_OK;
   const int64_t rows = offsets[B];
   if (rows > 0 && !X) return FV_E_INVAL;
-  if (precision != FV_PREC_FP32) return FV_E_UNSUPPORTED;
   const fv::Consts& c = gmm->c;
   if (rows > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
 
@@ -620,15 +705,14 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
     hipEvent_t t0 = timing_begin(s);
     if (path == Path::kFused) {
       const int grid = std::max(1, std::min(n_items, resident_fused(gmm->device, c.Wg)));
-      FV_HIP(fv::launch_stats(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid, partials, s));
+      FV_HIP(run_stats(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid, partials, s));
     } else {
       const int n_tiles = (int)((rows + fv::kTile - 1) / fv::kTile);
       const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
-      FV_HIP(fv::launch_lse(c, precision, Xd, vec_ok, rows, nullptr, n_tiles, grid1, lse, rows, s));
+      FV_HIP(run_lse(c, precision, Xd, vec_ok, rows, n_tiles, grid1, lse, rows, s));
       const int slices = c.Kp / fv::kCompsPerWave;
       const int grid2 = std::max(1, std::min(n_items, 2 * device_cu_count(gmm->device) / slices + 1));
-      FV_HIP(fv::launch_sliced(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid2, lse, rows,
-                               partials, s));
+      FV_HIP(run_sliced(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
     }
     timing_end(t0, 0, s);
   }

@@ -1,0 +1,254 @@
+// 16-bit operand forms of the two contractions (bf16 or fp16 on v_mfma_f32_32x32x16_*,
+// FP32 accumulation).
+//
+// Split form: every FP32 operand v is carried as hi = rne16(v), lo = rne16(v - hi) (v - hi is
+// exact in FP32) and a product is formed from three MFMAs, hi*hi + hi*lo + lo*hi; the lo*lo
+// term is dropped.  Plain form: hi only (one MFMA), kept as an accuracy control.
+//
+// 32x32x16 operand layout: lane (h, j) supplies 8 consecutive reduction indices 8h..8h+7 of
+// row j (A operand) or column j (B operand); C/D layout is the FP32 one.
+//
+// LDS tile of 32 rows, written once per tile by the loader:
+//   RM_hi / RM_lo  [32][2*DP + 8]   row-major [x, x^2]   -> E-step A operand (16 B per lane)
+//   XT_hi / XT_lo  [2*DP][40]       transposed, rows permuted by pos() -> statistics A operand
+// pos(row) swaps bits 2 and 3 of the row index.  The statistics k-step q of an MFMA consumes
+// the E-step result registers 8q..8q+7 of a lane in half h, i.e. rows
+// 16q + 8*(e>>2) + 4h + (e&3) for e = 0..7; pos() maps exactly these to 16q + 8h + e, so the
+// A operand is one contiguous 16-byte read.
+#pragma once
+
+#include "fv_device.h"
+
+namespace fv {
+namespace dev {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <class T>
+struct P16;
+
+template <>
+struct P16<__bf16> {
+  typedef bf16x8 v8;
+  __device__ __forceinline__ static f32x16 mfma(v8 a, v8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct P16<_Float16> {
+  typedef f16x8 v8;
+  __device__ __forceinline__ static f32x16 mfma(v8 a, v8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class T>
+__device__ __forceinline__ uint16_t bits16(T v) {
+  return __builtin_bit_cast(uint16_t, v);
+}
+
+// hi/lo split of an FP32 value (round to nearest even in both conversions).
+template <class T>
+__device__ __forceinline__ void split16(float v, T& hi, T& lo) {
+  hi = (T)v;
+  lo = (T)(v - (float)hi);
+}
+
+__device__ __forceinline__ constexpr int tpos(int row) {
+  return (row & ~12) | ((row & 4) << 1) | ((row & 8) >> 1);
+}
+
+template <int DP>
+struct Tile16 {
+  static constexpr int RS = 2 * DP + 8;   // row-major stride (16-bit elements)
+  static constexpr int TS = 40;           // transposed stride (16-bit elements)
+  static constexpr int kRM = kTile * RS;  // elements per row-major array
+  static constexpr int kXT = 2 * DP * TS;  // elements per transposed array
+  static constexpr int kElems = 2 * kRM + 2 * kXT;
+  static constexpr int kBlocks = (kTile / 4) * (DP / 4);  // 4x4 (row, feature) blocks of x
+  uint16_t* rm_hi;
+  uint16_t* rm_lo;
+  uint16_t* xt_hi;
+  uint16_t* xt_lo;
+  __device__ __forceinline__ explicit Tile16(uint16_t* base)
+      : rm_hi(base), rm_lo(base + kRM), xt_hi(base + 2 * kRM), xt_lo(base + 2 * kRM + kXT) {}
+};
+
+// Loader: NT threads; each 4x4 block of x (4 rows, 4 features) is fetched as four float4 into
+// registers (fetch), then converted and written to the four LDS arrays (store) together with
+// the matching block of x^2.
+template <int DP, int NT>
+struct TileIO16 {
+  using TL = Tile16<DP>;
+  static constexpr int kPer = (TL::kBlocks + NT - 1) / NT;
+
+  __device__ __forceinline__ static void fetch(f32x4 (&pre)[kPer][4], const float* __restrict__ X,
+                                               int D, bool vec_ok, int64_t row0, int valid,
+                                               int tid) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int blk = tid + q * NT;
+      const int rb = blk % (kTile / 4);  // consecutive threads: consecutive row blocks
+      const int c4 = (blk / (kTile / 4)) * 4;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        const int row = 4 * rb + rr;
+        if (blk < TL::kBlocks && row < valid) {
+          const float* src = X + (row0 + row) * (int64_t)D + c4;
+          if (vec_ok) {
+            if (c4 < D) v = *reinterpret_cast<const f32x4*>(src);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (c4 + e < D) v[e] = src[e];
+          }
+        }
+        pre[q][rr] = v;
+      }
+    }
+  }
+
+  template <class T, bool SPLIT>
+  __device__ __forceinline__ static void store(const TL& t, const f32x4 (&pre)[kPer][4], int tid) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int blk = tid + q * NT;
+      if (blk >= TL::kBlocks) continue;
+      const int rb = blk % (kTile / 4);
+      const int c4 = (blk / (kTile / 4)) * 4;
+#pragma unroll
+      for (int sq = 0; sq < 2; ++sq) {  // sq = 0: x, sq = 1: x^2
+        const int f0 = c4 + sq * DP;
+        uint16_t hi[4][4], lo[4][4];  // [row][feature]
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float v = sq ? pre[q][rr][e] * pre[q][rr][e] : pre[q][rr][e];
+            T h, l;
+            split16<T>(v, h, l);
+            hi[rr][e] = bits16<T>(h);
+            lo[rr][e] = SPLIT ? bits16<T>(l) : (uint16_t)0;
+          }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int row = 4 * rb + rr;
+          const u32x2 vh = {(unsigned)hi[rr][0] | ((unsigned)hi[rr][1] << 16),
+                            (unsigned)hi[rr][2] | ((unsigned)hi[rr][3] << 16)};
+          *reinterpret_cast<u32x2*>(t.rm_hi + row * TL::RS + f0) = vh;
+          if (SPLIT) {
+            const u32x2 vl = {(unsigned)lo[rr][0] | ((unsigned)lo[rr][1] << 16),
+                              (unsigned)lo[rr][2] | ((unsigned)lo[rr][3] << 16)};
+            *reinterpret_cast<u32x2*>(t.rm_lo + row * TL::RS + f0) = vl;
+          }
+        }
+        const int p0 = tpos(4 * rb);  // four consecutive rows land on four consecutive slots
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const u32x2 vh = {(unsigned)hi[0][e] | ((unsigned)hi[1][e] << 16),
+                            (unsigned)hi[2][e] | ((unsigned)hi[3][e] << 16)};
+          *reinterpret_cast<u32x2*>(t.xt_hi + (f0 + e) * TL::TS + p0) = vh;
+          if (SPLIT) {
+            const u32x2 vl = {(unsigned)lo[0][e] | ((unsigned)lo[1][e] << 16),
+                              (unsigned)lo[2][e] | ((unsigned)lo[3][e] << 16)};
+            *reinterpret_cast<u32x2*>(t.xt_lo + (f0 + e) * TL::TS + p0) = vl;
+          }
+        }
+      }
+    }
+  }
+};
+
+// E-step, 16-bit operands.  bh/bl: per k-step s (16 features), the lane's 8 constants
+// A[16s + 8h + e][comp] as hi/lo fragments.  Chains of two k-steps (32 features) are joined
+// with TwoSum exactly as in the FP32 form.
+template <int DP, class T, bool SPLIT>
+__device__ __forceinline__ void estep16(const Tile16<DP>& t, int j, int h,
+                                        const typename P16<T>::v8 (&bh)[2 * DP / 16],
+                                        const typename P16<T>::v8 (&bl)[2 * DP / 16], float cval,
+                                        f32x16& hi, f32x16& lo) {
+  using V = typename P16<T>::v8;
+  constexpr int NS = 2 * DP / 16;
+  const uint16_t* ah = t.rm_hi + j * Tile16<DP>::RS + 8 * h;
+  const uint16_t* al = t.rm_lo + j * Tile16<DP>::RS + 8 * h;
+#pragma unroll
+  for (int ch = 0; ch < NS / 2; ++ch) {
+    f32x16 a;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = (ch == 0) ? cval : 0.f;
+#pragma unroll
+    for (int s = 2 * ch; s < 2 * ch + 2; ++s) {
+      const V xh = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(ah + 16 * s));
+      a = P16<T>::mfma(xh, bh[s], a);
+      if (SPLIT) {
+        const V xl = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(al + 16 * s));
+        a = P16<T>::mfma(xh, bl[s], a);
+        a = P16<T>::mfma(xl, bh[s], a);
+      }
+    }
+    if (ch == 0) {
+      hi = a;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lo[r] = 0.f;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float tt = hi[r] + a[r];
+        const float bp = tt - hi[r];
+        const float err = (hi[r] - (tt - bp)) + (a[r] - bp);
+        hi[r] = tt;
+        lo[r] += err;
+      }
+    }
+  }
+}
+
+// Statistics, 16-bit operands: acc[b] += XT[32b + j][rows] . gamma[rows][comp], gamma split
+// into hi/lo from the E-step result registers (k-step q uses registers 8q..8q+7).
+template <int DP, class T, bool SPLIT>
+__device__ __forceinline__ void stats16(const Tile16<DP>& t, int j, int h, const f32x16& gam,
+                                        f32x16 (&acc)[2 * DP / 32]) {
+  using V = typename P16<T>::v8;
+  constexpr int NB = 2 * DP / 32;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    V gh, gl;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      T hh, ll;
+      split16<T>(gam[8 * q + e], hh, ll);
+      gh[e] = hh;
+      gl[e] = SPLIT ? ll : (T)0.f;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int off = (32 * b + j) * Tile16<DP>::TS + 16 * q + 8 * h;
+      const V xh = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(t.xt_hi + off));
+      acc[b] = P16<T>::mfma(xh, gh, acc[b]);
+      if (SPLIT) {
+        const V xl = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(t.xt_lo + off));
+        acc[b] = P16<T>::mfma(xh, gl, acc[b]);
+        acc[b] = P16<T>::mfma(xl, gh, acc[b]);
+      }
+    }
+  }
+}
+
+// Loads the lane's E-step constant fragments: fragment (s, h, comp) holds A[16s + 8h + e][comp]
+// for e = 0..7, stored contiguously at ((s*2 + h) * Kp + comp) * 8.
+template <int DP, class T>
+__device__ __forceinline__ void load_frags(const uint16_t* __restrict__ fr, int Kp, int comp, int h,
+                                           typename P16<T>::v8 (&b)[2 * DP / 16]) {
+  using V = typename P16<T>::v8;
+#pragma unroll
+  for (int s = 0; s < 2 * DP / 16; ++s)
+    b[s] = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(fr + ((size_t)(s * 2 + h) * Kp + comp) * 8));
+}
+
+}  // namespace dev
+}  // namespace fv

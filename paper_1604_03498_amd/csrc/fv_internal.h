@@ -23,7 +23,8 @@ struct Consts {
   // E-step operand, log2(e)-scaled, [2*DP][Kp] f32: rows 0..DP-1 multiply x, rows DP..2DP-1
   // multiply x^2; padded rows and columns are zero.
   const float* A32;
-  // hi/lo splits of A32 for the bf16 and fp16 forms: [2*DP][Kp] each (as 16-bit words)
+  // hi/lo splits of A32 for the bf16 and fp16 forms, as MFMA operand fragments: fragment
+  // (s, h, comp) holds A[16s + 8h + e][comp], e = 0..7, at ((s*2 + h) * Kp + comp) * 8
   const uint16_t* Abf_hi;
   const uint16_t* Abf_lo;
   const uint16_t* Ah_hi;
@@ -103,5 +104,29 @@ hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* 
 
 // Blocks per frame of the assembly step (size of normpart per frame).
 int finalize_blocks(const Consts& c);
+
+// ---- 16-bit operand forms (one translation unit per form) --------------------------------
+struct Frags16 {
+  const uint16_t* hi;
+  const uint16_t* lo;
+};
+
+#define FV_DECLARE_FORM(sfx)                                                                  \
+  hipError_t launch_stats16_##sfx(const Consts& c, const Frags16& fr, const float* X,          \
+                                  bool vec_ok, int64_t N, int P, const Item* items,            \
+                                  int n_items, int grid, float* partials, hipStream_t stream); \
+  hipError_t launch_lse16_##sfx(const Consts& c, const Frags16& fr, const float* X,            \
+                                bool vec_ok, int64_t N, const Item* items, int n_items,        \
+                                int grid, float2* lse, int64_t lse_stride,                     \
+                                hipStream_t stream);                                           \
+  hipError_t launch_sliced16_##sfx(const Consts& c, const Frags16& fr, const float* X,         \
+                                   bool vec_ok, int64_t N, int P, const Item* items,           \
+                                   int n_items, int grid, const float2* lse,                   \
+                                   int64_t lse_stride, float* partials, hipStream_t stream);   \
+  int sliced16_waves_##sfx(int DP);
+FV_DECLARE_FORM(bf16s)
+FV_DECLARE_FORM(f16s)
+FV_DECLARE_FORM(bf16)
+#undef FV_DECLARE_FORM
 
 }  // namespace fv
