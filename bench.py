@@ -1,17 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the Fisher-vector encoding hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload frame|batch]
-                    [--precision fp32] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp32,bf16_split,fp16_split]
+                    [--no-batch] [--no-cpu-baseline] [--calib-copy-mb M]
 
 One step = one full pass of the encoder (load + square, E-step contraction, soft assignment,
-statistics contraction, chunk reduction, u/v assembly, signed square root, L2) over one batch
-of synthetic input already resident in device memory:
-  * frame (default): one 320x240 frame, N = 8,000 descriptors, D = 64, K = 256 GMM,
-    5% uniform outliers, via fv_encode;
-  * batch: 64 frames with N_f uniform in [2,000, 20,000] via fv_encode_batch.
-The GMM load (per-model constant precompute) happens once before timing and is reported
-separately.  Prints one JSON line.
+statistics contraction, chunk reduction, u/v assembly, signed square root, L2) over one frame
+of synthetic input already resident in device memory: a 320x240 frame, N = 8,000
+descriptors, D = 64, K = 256 GMM, 5% uniform outliers (fv_encode).  `value` is FP32
+descriptors/s for that workload; the other arithmetic forms (bf16 / fp16 hi-lo split) are
+timed the same way and reported under "forms", and the 64-frame batch (N_f uniform in
+[2000, 20000], fv_encode_batch) under "batch" as context.  The GMM load (per-model constant
+precompute) happens once before timing and is reported separately.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,8 +26,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
+# MI355X dense peaks: FP32 MFMA 157.3 TFLOP/s; BF16 / FP16 MFMA 2.5 PFLOP/s.
 PEAK_TFLOPS = {"fp32": 157.3, "bf16_split": 2500.0, "fp16_split": 2500.0, "bf16": 2500.0}
 PREC_CODE = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3}
+PRODUCTS = {"fp32": 1, "bf16_split": 3, "fp16_split": 3, "bf16": 1}
+DTYPE = {"fp32": "f32", "bf16_split": "bf16x3", "fp16_split": "f16x3", "bf16": "bf16"}
+METRIC = "descriptors/sec encoded (K=256,D=64), BF16-split vs FP32; p99 frame latency"
 
 
 def log(*a):
@@ -37,144 +41,185 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=("frame", "batch"), default="frame")
-    ap.add_argument("--precision", choices=tuple(PREC_CODE), default="fp32")
-    ap.add_argument("--latency-samples", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--forms", default="fp32,bf16_split,fp16_split")
+    ap.add_argument("--latency-samples", type=int, default=300)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (HBM-counter scale)")
     return ap.parse_args()
 
 
-def cpu_baseline(g, X, off, got, seconds):
+def path_of(K, N, n_cu, fv_path_env):
+    """The statistics path the library picks for one frame (mirrors its rule)."""
+    if fv_path_env in ("fused", "split"):
+        return fv_path_env
+    if K > 256:
+        return "split"
+    return "split" if N < 4 * 32 * n_cu else "fused"
+
+
+def time_form(fv, torch, h, Xd, off, out, form, steps, warmup, stream, lat_samples, batch):
+    prec = PREC_CODE[form]
+
+    def step():
+        if batch:
+            fv.encode_batch(h, Xd, off, out=out, precision=prec, flags=fv.ASYNC, stream=stream)
+        else:
+            fv.encode(h, Xd, out=out, precision=prec, flags=fv.ASYNC, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    fv.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st_ms, st_n = fv.kernel_timing_read(0)
+    fi_ms, fi_n = fv.kernel_timing_read(1)
+    fv.kernel_timing(False)
+    lat = []
+    if lat_samples:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(lat_samples):
+            e0.record(stream)
+            step()
+            e1.record(stream)
+            e1.synchronize()
+            lat.append(e0.elapsed_time(e1))
+    torch.cuda.synchronize()
+    return elapsed, st_ms / max(st_n, 1), st_n, fi_ms / max(fi_n, 1), np.array(lat)
+
+
+def roofline(form, K, D, ndesc, stats_avg_ms, path):
+    alg = 8.0 * K * D * ndesc                      # algorithmic flops of the two contractions
+    execd = alg * PRODUCTS[form] * (1.5 if path == "split" else 1.0)
+    achieved = alg / (stats_avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[form]
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "mfma_util": round(execd / (stats_avg_ms * 1e-3) / 1e12 / peak, 4),
+            "kernel": ("fused statistics kernel" if path == "fused" else
+                       "two-pass statistics: row log-sum-exp pass + component-sliced pass"),
+            "kernel_avg_us": round(stats_avg_ms * 1e3, 3)}
+
+
+def cpu_baseline(g, frames, seconds):
     """The FP64 oracle on the host cores over a bounded sample of the same workload: whole
-    frames of the workload are encoded (in parallel over frames) until `seconds` elapse.
-    Also reports the GPU result's error against the oracle on the first frame."""
+    copies of the workload frame are encoded, spread over threads, until `seconds` elapse."""
     import oracle
-    from oracle.metrics import errors
     nthreads = max(1, min(16, os.cpu_count() or 1))
-    B = off.size - 1
-    frames = [(X[off[b]:off[b + 1]]) for b in range(B)]
-    ref0 = oracle.encode(frames[0], g.weights, g.means, g.variances)
-    err = errors(got[0], ref0)
-    done_desc, t0 = 0, time.perf_counter()
-    n_frames = 0
+    done, n_frames, t0 = 0, 0, time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        idx = [(n_frames + i) % B for i in range(nthreads)]
+        idx = [(n_frames + i) % len(frames) for i in range(nthreads)]
         Xs = np.concatenate([frames[i] for i in idx])
         o = np.zeros(len(idx) + 1, np.int64)
         o[1:] = np.cumsum([frames[i].shape[0] for i in idx])
         oracle.encode_batch(Xs, o, g.weights, g.means, g.variances, nthreads=nthreads)
-        done_desc += int(o[-1])
+        done += int(o[-1])
         n_frames += len(idx)
     dt = time.perf_counter() - t0
-    return {"value": done_desc / dt, "unit": "descriptors/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{n_frames} frames of the workload ({done_desc} descriptors) in {dt:.1f} s, "
-                      f"FP64 C oracle, frames spread over {nthreads} threads"}, err
+    return {"value": done / dt, "unit": "descriptors/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n_frames} encodes of the workload frame ({done} descriptors) in "
+                      f"{dt:.1f} s; FP64 C oracle, whole frames spread over {nthreads} threads"}
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "single-GPU build: run with --gpus 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md, not implemented)"}))
         sys.exit(2)
     import torch
     import fvsynth
     import paper_1604_03498_amd as fv
 
     dev = torch.device("cuda:0")
-    if a.workload == "frame":
-        wname = "c2_frame_k256_d64_n8000"
-    else:
-        wname = "c4_batch64_k256_d64"
-    g, X, off = fvsynth.workload(wname)
-    K, D = g.K, g.D
-    B = off.size - 1
-    total_desc = int(off[-1])
-    prec = PREC_CODE[a.precision]
-
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    forms = [f for f in a.forms.split(",") if f]
+    g, X, off = fvsynth.workload("c2_frame_k256_d64_n8000")
+    K, D, N = g.K, g.D, int(X.shape[0])
     t0 = time.perf_counter()
     h = fv.gmm_load(g.weights, g.means, g.variances, device=0)
     gmm_load_ms = (time.perf_counter() - t0) * 1e3
     Xd = torch.from_numpy(X).to(dev)
-    if a.workload == "frame":
-        out = torch.empty(2 * K * D, dtype=torch.float32, device=dev)
-    else:
-        out = torch.empty(B, 2 * K * D, dtype=torch.float32, device=dev)
     stream = torch.cuda.Stream(device=dev)
+    path = path_of(K, N, n_cu, os.environ.get("FV_PATH"))
 
-    def step():
-        if a.workload == "frame":
-            fv.encode(h, Xd, out=out, precision=prec, flags=fv.ASYNC, stream=stream)
-        else:
-            fv.encode_batch(h, Xd, off, out=out, precision=prec, flags=fv.ASYNC, stream=stream)
+    results, outputs = {}, {}
+    for form in forms:
+        out = torch.empty(2 * K * D, dtype=torch.float32, device=dev)
+        log(f"[bench] frame form={form} path={path} warmup={a.warmup} steps={a.steps}")
+        el, st_avg, st_n, fi_avg, lat = time_form(fv, torch, h, Xd, off, out, form, a.steps,
+                                                   a.warmup, stream, a.latency_samples, False)
+        r = {"value": N * a.steps / el, "ms_per_step": el * 1e3 / a.steps,
+             "roofline": roofline(form, K, D, N, st_avg, path),
+             "finalize_avg_us": round(fi_avg * 1e3, 3), "launches": st_n}
+        if lat.size:
+            r["latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                               "max": float(lat.max()), "samples": int(lat.size)}
+        results[form] = r
+        outputs[form] = out.cpu().numpy()
+        log(f"[bench]   {r['value']:.4e} desc/s, {r['ms_per_step']:.4f} ms/step, "
+            f"stats {r['roofline']['kernel_avg_us']} us")
 
-    log(f"[bench] workload={wname} precision={a.precision} warmup={a.warmup} steps={a.steps}")
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
+    batch = {}
+    if not a.no_batch:
+        gb, Xb, offb = fvsynth.workload("c4_batch64_k256_d64")
+        Xbd = torch.from_numpy(Xb).to(dev)
+        hb = h  # same GMM (K=256, D=64, seed 0)
+        bpath = os.environ.get("FV_PATH") if os.environ.get("FV_PATH") in ("fused", "split") else "fused"
+        for form in forms:
+            outb = torch.empty(offb.size - 1, 2 * K * D, dtype=torch.float32, device=dev)
+            log(f"[bench] batch form={form} steps={a.batch_steps}")
+            el, st_avg, st_n, fi_avg, _ = time_form(fv, torch, hb, Xbd, offb, outb, form,
+                                                     a.batch_steps, 2, stream, 0, True)
+            nb = int(offb[-1])
+            batch[form] = {"value": nb * a.batch_steps / el, "ms_per_step": el * 1e3 / a.batch_steps,
+                           "roofline": roofline(form, K, D, nb, st_avg, bpath),
+                           "finalize_avg_us": round(fi_avg * 1e3, 3)}
+            log(f"[bench]   {batch[form]['value']:.4e} desc/s")
+        batch["config"] = {"workload": "c4_batch64_k256_d64", "frames": int(offb.size - 1),
+                           "descriptors": int(offb[-1])}
 
-    # ---- timed region: K steps, synchronised on both sides; kernel durations via HIP events
-    fv.kernel_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stats_ms, stats_n = fv.kernel_timing_read(0)
-    fin_ms, fin_n = fv.kernel_timing_read(1)
-    fv.kernel_timing(False)
-    ms_per_step = elapsed * 1e3 / a.steps
-    value = total_desc * a.steps / elapsed
-    log(f"[bench] {ms_per_step:.4f} ms/step, {value:.4e} desc/s")
+    if a.calib_copy_mb > 0:
+        n = a.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {a.calib_copy_mb} MiB done")
 
-    # ---- per-frame latency (one encode at a time, event-timed on the stream)
-    lat = []
-    if a.workload == "frame":
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        for _ in range(a.latency_samples):
-            ev0.record(stream)
-            step()
-            ev1.record(stream)
-            ev1.synchronize()
-            lat.append(ev0.elapsed_time(ev1))
-    lat = np.array(lat) if lat else None
-
-    # ---- roofline of the dominant kernel (statistics): algorithmic flops per launch
-    flops_per_desc = 8 * K * D
-    stats_avg_ms = stats_ms / max(stats_n, 1)
-    achieved_tflops = flops_per_desc * total_desc / (stats_avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[a.precision]
-    roofline = {"bound": "mfma", "achieved": round(achieved_tflops, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved_tflops / peak, 4), "traffic": None,
-                "kernel": "stats (fused E-step + soft assignment + statistics)",
-                "kernel_avg_us": round(stats_avg_ms * 1e3, 3), "launches": stats_n,
-                "finalize_avg_us": round(fin_ms / max(fin_n, 1) * 1e3, 3)}
-
+    prim = forms[0]
+    res = results[prim]
     result = {
-        "metric": "descriptors/sec encoded (K=256,D=64), BF16-split vs FP32; p99 frame latency",
-        "value": value, "unit": "descriptors/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16_split": "bf16x3", "fp16_split": "f16x3", "bf16": "bf16"}[a.precision],
+        "metric": METRIC, "value": res["value"], "unit": "descriptors/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prim],
         "data": "synthetic (seeded GMM-sampled descriptors, 5% uniform outliers)",
-        "config": {"workload": wname, "K": K, "D": D, "frames": B, "descriptors": total_desc,
-                   "precision": a.precision},
+        "config": {"workload": "c2_frame_k256_d64_n8000", "K": K, "D": D, "frames": 1,
+                   "descriptors": N, "precision": prim, "path": path},
+        "roofline": res["roofline"], "latency_ms": res.get("latency_ms"),
         "gmm_load_ms": round(gmm_load_ms, 3),
-        "roofline": roofline,
+        "forms": {f: {k: v for k, v in r.items()} for f, r in results.items()},
     }
-    if lat is not None:
-        result["latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                                "max": float(lat.max()), "samples": int(lat.size),
-                                "what": "one fv_encode (device-resident X and out), HIP events"}
+    if batch:
+        result["batch"] = batch
     if not a.no_cpu_baseline:
-        got = out.detach().cpu().numpy().reshape(B, -1)
-        cb, err = cpu_baseline(g, X, off, got, a.cpu_seconds)
-        result["cpu_baseline"] = cb
-        result["error_vs_oracle_frame0"] = err
+        import oracle
+        from oracle.metrics import errors
+        ref = oracle.encode_gmm(X, g)
+        for f in forms:
+            result["forms"][f]["error_vs_oracle"] = errors(outputs[f], ref)
+        result["cpu_baseline"] = cpu_baseline(g, [X], a.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 

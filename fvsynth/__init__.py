@@ -6,7 +6,7 @@ It contains none of the Fisher-vector arithmetic, so the GPU path and the
 FP64 oracle can both consume it without sharing any of the method.
 
 The paper's inputs (dense-SIFT descriptors PCA-reduced to ~80 dims, a 256-component
-GMM trained on Caltech256 / pubfig; Sec. 2.1 and Sec. 4) are not available, so
+GMM trained on Caltech256 / pubfig; Sec. 3.1 and Sec. 4) are not available, so
 these generators stand in for them with the paper's shapes (K=256 components,
 D of 64-82, ~10^4 descriptors per 320x240 frame).
 """

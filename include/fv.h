@@ -3,9 +3,9 @@
  * Instinct MI355X (gfx950).  C ABI: plain pointers and sizes, no C++ or framework types.
  *
  * The operation (Ma et al., "GPU-FV: Realtime Fisher Vector and Its Applications in Video
- * Monitoring", ICMR 2016, Sec. 2.1 and Algorithm 1; normalisation of the improved Fisher
- * vector of Perronnin et al. / Sanchez et al. that the paper cites and that its experiments
- * use via "the same encoding scheme as VLFeat", Sec. 4):
+ * Monitoring", ICMR 2016, Sec. 3.1 and Algorithm 1; normalisation of the improved Fisher
+ * vector of Perronnin et al. / Sanchez et al., which the paper cites and whose VLFeat
+ * implementation its experiments follow, Sec. 4):
  *
  *   input   N descriptors x_t in R^D; a K-component diagonal GMM (weights w_k, means mu_k,
  *           variances var_k = sigma_k^2)
@@ -65,8 +65,8 @@ typedef struct fv_gmm fv_gmm;
 void fv_limits(int* max_K, int* max_D);
 
 /*
- * Load a diagonal GMM onto device `device` (Algorithm 1, "Compute sqrt(sigma^-1)"; here the
- * whole per-model constant set is evaluated once, in double precision, on the host:
+ * Load a diagonal GMM onto device `device` (Algorithm 1 precomputes the inverse standard
+ * deviation once per model; here the whole per-model constant set is evaluated once, in double precision, on the host:
  * 1/sigma, 1/sigma^2, the E-step operand [mu/sigma^2 ; -1/(2 sigma^2)] and offsets
  * ln w_k - 1/2 sum_d ln sigma^2_kd - 1/2 sum_d mu_kd^2/sigma^2_kd, and the block scales
  * 1/sqrt(w_k), 1/sqrt(2 w_k)).

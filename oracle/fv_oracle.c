@@ -5,11 +5,11 @@
  * code.  The GPU library never links, loads or calls it, and this file shares no code,
  * headers, tables or constants with it.
  *
- * What it computes (Ma et al., "GPU-FV", ICMR'16, Sec. 2.1, Algorithm 1, and the improved
+ * What it computes (Ma et al., GPU-FV, ICMR'16, Sec. 3.1 and Algorithm 1, and the improved
  * Fisher vector of Perronnin et al. that the paper cites for its encoding):
- *   1. s_kd = 1/sqrt(var_kd)                            (Alg. 1: precompute the inverse std)
+ *   1. s_kd = 1/sqrt(var_kd)                            (Alg. 1 precomputes the inverse std)
  *   2. per descriptor x_t and component k:
- *        delta_tk = sum_d ((x_td - mu_kd) * s_kd)^2     ("distance": diagonal Mahalanobis)
+ *        delta_tk = sum_d ((x_td - mu_kd) * s_kd)^2     (squared diagonal Mahalanobis distance)
  *        l_tk     = ln w_k - 1/2 sum_d ln var_kd - 1/2 delta_tk   (Gaussian log-joint; the
  *                   -D/2 ln(2 pi) constant cancels in the posterior)
  *        m_t      = max_k l_tk

@@ -1,6 +1,6 @@
 // gfx950 (CDNA4) statistics kernels for Fisher-vector encoding against a diagonal GMM.
 //
-// Fused kernel (E-step + soft assignment + moment accumulation in one pass; Sec. 2.1 and
+// Fused kernel (E-step + soft assignment + moment accumulation in one pass; Sec. 3.1 and
 // Algorithm 1 of the GPU-FV paper, its two GPU phases re-designed for MFMA):
 //   * A workgroup of W wavefronts owns a group of 32*W components; wave w owns 32 of them
 //     and keeps its slice of the E-step operand A = [mu/sigma^2 ; -1/(2 sigma^2)]
