@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serving-seconds", type=float, default=4.0,
+                    help="measured seconds of each open-loop serving run (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (HBM-counter scale)")
     return ap.parse_args()
@@ -109,6 +111,85 @@ def roofline(form, K, D, ndesc, stats_avg_ms, path):
             "kernel": ("fused statistics kernel" if path == "fused" else
                        "two-pass statistics: row log-sum-exp pass + component-sliced pass"),
             "kernel_avg_us": round(stats_avg_ms * 1e3, 3)}
+
+
+def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_streams=2):
+    """Open-loop serving run: 16 camera streams, Poisson arrivals at 30 Hz each, frames of
+    8,000-32,000 descriptors (320x240 .. 640x480), D = 80, K = 512.  Latency is measured from
+    each frame's scheduled arrival time to the completion of its encode (so a late submit
+    counts against the server), over the frames that arrive after the warm-up."""
+    import threading
+    import fvsynth
+    g = fvsynth.gmm(512, 80, 0)
+    events, sizes = fvsynth.serving_plan(duration_s=warm_s + seconds, pool=pool)
+    frames = {(st, p): fvsynth.frame(g, sizes[st], 100000 + 100 * st + p, 0.05)
+              for st in range(len(sizes)) for p in range(pool)}
+    h = fv.gmm_load(g.weights, g.means, g.variances, device=0)
+    cfg = fv.server_config(precision=PREC_CODE[form], n_streams=n_streams,
+                           hbm_budget_bytes=int(budget_bytes))
+    srv = fv.Server(h, cfg)
+    for st in range(len(sizes)):          # warm every frame size once (buffers, code objects)
+        t = srv.submit(frames[(st, 0)])
+        while srv.next_done(1000.0) != t:
+            pass
+        srv.poll(t, want_out=False)
+    srv.stats(reset=True)
+    sub = {}
+    done = {}
+    n_events = len(events)
+    finished = threading.Event()
+
+    def collect():
+        while len(done) < n_events:
+            t = srv.next_done(100.0)
+            if t is None:
+                continue
+            rc, _, stt = srv.poll(t, want_out=False)
+            done[t] = (rc, stt)
+        finished.set()
+
+    th = threading.Thread(target=collect, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    for (t_arr, st, p) in events:
+        wait = t0 + t_arr - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        ts = time.perf_counter()
+        while True:
+            rc, tk = srv.try_submit(frames[(st, p)])
+            if rc == fv.OK:
+                break
+            time.sleep(0.0005)
+        sub[tk] = (t_arr, ts - t0, sizes[st])
+    finished.wait(timeout=120.0)
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    lat, rows, fails, frames_in_launch = [], 0, 0, []
+    for tk, (t_arr, t_sub, n) in sub.items():
+        if tk not in done or t_arr < warm_s:
+            continue
+        rc, stt = done[tk]
+        if rc != fv.OK:
+            fails += 1
+            continue
+        lat.append((stt["t_done_us"] - stt["t_submit_us"]) * 1e-3 + (t_sub - t_arr) * 1e3)
+        rows += n
+        frames_in_launch.append(stt["batch_frames"])
+    lat = np.array(lat)
+    return {"form": form, "streams": len(sizes), "rate_hz_per_stream": 30.0,
+            "frame_sizes": sorted(set(sizes)), "K": 512, "D": 80,
+            "measured_s": seconds, "frames": int(lat.size), "failed": fails,
+            "offered_desc_per_s": float(sum(sizes) * 30.0),
+            "throughput_desc_per_s": rows / seconds,
+            "latency_ms_from_arrival": {"p50": float(np.percentile(lat, 50)) if lat.size else None,
+                                        "p99": float(np.percentile(lat, 99)) if lat.size else None,
+                                        "max": float(lat.max()) if lat.size else None},
+            "mean_frames_per_launch": float(np.mean(frames_in_launch)) if frames_in_launch else None,
+            "budget_bytes": int(budget_bytes), "peak_admitted_bytes": int(stats["peak_admitted_bytes"]),
+            "gpu_busy_fraction": stats["busy_s"] / max(wall - warm_s, 1e-9), "n_streams": n_streams,
+            "input": "host memory (submit copies into pinned staging; H2D inside the launch)"}
 
 
 def cpu_baseline(g, frames, seconds):
@@ -189,6 +270,15 @@ def main():
         batch["config"] = {"workload": "c4_batch64_k256_d64", "frames": int(offb.size - 1),
                            "descriptors": int(offb[-1])}
 
+    serving = []
+    if a.serving_seconds > 0:
+        for budget in (2 << 30, 64 << 20):
+            log(f"[bench] serving budget={budget >> 20} MiB for {a.serving_seconds} s")
+            r = run_serving(fv, a.serving_seconds, 1.0, budget)
+            log(f"[bench]   p50 {r['latency_ms_from_arrival']['p50']:.3f} ms, p99 "
+                f"{r['latency_ms_from_arrival']['p99']:.3f} ms, {r['throughput_desc_per_s']:.3e} desc/s")
+            serving.append(r)
+
     if a.calib_copy_mb > 0:
         n = a.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -213,6 +303,8 @@ def main():
     }
     if batch:
         result["batch"] = batch
+    if serving:
+        result["serving"] = serving
     if not a.no_cpu_baseline:
         import oracle
         from oracle.metrics import errors

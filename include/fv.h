@@ -124,6 +124,83 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
 int fv_kernel_timing(int enable);
 int fv_kernel_timing_read(int which, double* total_ms, int64_t* launches);
 
+/* ---- serving ------------------------------------------------------------------------------
+ * A server keeps one GMM and its own HIP streams, accepts frames of any size from any thread,
+ * and encodes them with continuous batching: a scheduler thread admits queued requests in
+ * arrival order while their device-memory footprint fits the budget, groups them into one
+ * batched launch (fv_encode_batch semantics, so each frame's result is bitwise the same alone
+ * or in any mix), and runs up to n_streams launches concurrently; requests that arrive while
+ * others are on the GPU are admitted as soon as a stream and budget are free.  The paper runs
+ * one frame at a time for its real-time video applications (Sec. 4.2); serving is new here.
+ */
+typedef struct fv_server fv_server;
+
+#define FV_EXEC_HIP 0   /* encode on the GPU */
+#define FV_EXEC_FAKE 1  /* host-only test executor: no device use; a batch "completes" after
+                           fake_us_per_krow microseconds per 1000 rows and yields zeros */
+
+typedef struct fv_server_config {
+  size_t hbm_budget_bytes;  /* device bytes in-flight batches may hold (0 = unlimited) */
+  int precision;            /* FV_PREC_* */
+  unsigned flags;           /* FV_NO_POWER_NORM / FV_NO_L2_NORM only */
+  int max_queue;            /* requests waiting for admission (<= 0: 4096) */
+  int n_streams;            /* concurrent launches (<= 0: 2) */
+  int max_batch_frames;     /* frames per launch (<= 0: 64) */
+  int64_t max_batch_rows;   /* rows per launch (<= 0: 262144) */
+  double deadline_ms;       /* a request not admitted within this time fails with
+                               FV_E_TIMEOUT (<= 0: no deadline) */
+  int executor;             /* FV_EXEC_HIP or FV_EXEC_FAKE */
+  int fake_K, fake_D;       /* FV_EXEC_FAKE only: output size 2*K*D when gmm is NULL */
+  double fake_us_per_krow;  /* FV_EXEC_FAKE only */
+  int fake_fail_every;      /* FV_EXEC_FAKE only: every n-th batch fails with FV_E_DEVICE */
+} fv_server_config;
+
+typedef struct fv_req_stats {
+  double t_submit_us, t_admit_us, t_start_us, t_done_us;  /* server clock (steady, microseconds
+                                                              since fv_server_create) */
+  int64_t rows;
+  int batch_frames;  /* frames in the launch that carried this request */
+  int status;        /* FV_OK or the failure code */
+} fv_req_stats;
+
+typedef struct fv_server_stats {
+  int64_t submitted, completed, failed, rejected;
+  int64_t launches;
+  int64_t rows_done;
+  int queued, in_flight;
+  size_t admitted_bytes, peak_admitted_bytes;
+  double p50_ms, p99_ms, max_ms;  /* submit-to-done latency of completed requests */
+  double busy_s;                  /* wall time with at least one launch in flight */
+} fv_server_stats;
+
+/* Fill a config with the defaults above (budget unlimited, FP32, HIP executor). */
+void fv_server_config_default(fv_server_config* cfg);
+
+/* Create a server for `gmm` (may be NULL only with FV_EXEC_FAKE).  The handle must outlive the
+ * server.  Errors: FV_E_INVAL, FV_E_NOMEM, FV_E_DEVICE. */
+int fv_server_create(const fv_gmm* gmm, const fv_server_config* cfg, fv_server** out);
+
+/* Stop the scheduler (waits for in-flight launches) and free everything; unpolled results are
+ * discarded. */
+int fv_server_destroy(fv_server* srv);
+
+/* Enqueue one frame X [N x D] (host memory; copied before return, so the caller may reuse X).
+ * Thread-safe and non-blocking.  Returns FV_OK and a ticket, FV_E_BUDGET if the frame can never
+ * fit the budget, FV_E_AGAIN if the queue is full, FV_E_INVAL for bad arguments. */
+int fv_server_submit(fv_server* srv, const float* X, int64_t N, uint64_t* ticket);
+
+/* Result of a ticket: FV_PENDING while queued or running; FV_OK with out (host, 2*K*D floats,
+ * may be NULL) and st (may be NULL) filled -- the ticket is then consumed; a failure code
+ * (FV_E_TIMEOUT, FV_E_DEVICE) also consumes it; FV_E_NOTFOUND for an unknown ticket. */
+int fv_server_poll(fv_server* srv, uint64_t ticket, float* out, fv_req_stats* st);
+
+/* Wait up to timeout_ms (< 0: forever) for any request to finish and return its ticket
+ * (each finished ticket is reported once).  FV_PENDING on timeout. */
+int fv_server_next_done(fv_server* srv, double timeout_ms, uint64_t* ticket);
+
+/* Aggregate counters and latency percentiles since creation (or the last reset). */
+int fv_server_get_stats(fv_server* srv, fv_server_stats* st, int reset);
+
 /* Static description of a status code. */
 const char* fv_strerror(int code);
 

@@ -17,11 +17,6 @@
 #include "fv.h"
 #include "fv_internal.h"
 
-struct fv_gmm {
-  int K = 0, D = 0, device = 0;
-  fv::Consts c{};
-  void* dev_block = nullptr;  // one allocation holding every constant array
-};
 
 namespace {
 
@@ -313,6 +308,28 @@ void timing_end(hipEvent_t start, int which, hipStream_t s) {
 }
 
 }  // namespace
+
+namespace fv {
+size_t batch_device_bytes(const Consts& c, const int64_t* sizes, int B) {
+  const bool split = choose_batch(c) == Path::kSplit;
+  const int P = batch_chunk();
+  int64_t rows = 0, items = 0, groups = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t ni = (sizes[b] + P - 1) / P;
+    rows += sizes[b];
+    items += ni;
+    groups += (ni + kGroupItems - 1) / kGroupItems;
+  }
+  const size_t out_len = (size_t)2 * c.K * c.D;
+  size_t n = align256((size_t)items * slot_floats(c) * 4) + align256((size_t)groups * slot_floats(c) * 8) +
+             align256((size_t)B * finalize_blocks(c) * 8) +
+             (split ? align256((size_t)lse_groups(c) * rows * 8) : 0) +
+             align256((size_t)B * sizeof(Frame)) + align256((size_t)items * sizeof(Item)) +
+             align256((size_t)groups * sizeof(Group));
+  n += align256((size_t)rows * c.D * 4) + align256((size_t)B * out_len * 4);
+  return n;
+}
+}  // namespace fv
 
 extern "C" {
 

@@ -105,6 +105,10 @@ hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* 
 // Blocks per frame of the assembly step (size of normpart per frame).
 int finalize_blocks(const Consts& c);
 
+// Device bytes one fv_encode_batch call needs for frames of the given sizes (workspace plus
+// device-resident X and out), used by the server's admission control.
+size_t batch_device_bytes(const Consts& c, const int64_t* sizes, int B);
+
 // ---- 16-bit operand forms (one translation unit per form) --------------------------------
 struct Frags16 {
   const uint16_t* hi;
@@ -130,3 +134,10 @@ FV_DECLARE_FORM(bf16)
 #undef FV_DECLARE_FORM
 
 }  // namespace fv
+
+// The public handle (opaque in the C ABI).
+struct fv_gmm {
+  int K = 0, D = 0, device = 0;
+  fv::Consts c{};
+  void* dev_block = nullptr;  // one allocation holding every constant array
+};

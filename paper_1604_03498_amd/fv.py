@@ -19,7 +19,35 @@ X_DEVICE, OUT_DEVICE, NO_POWER_NORM, NO_L2_NORM, ASYNC = 1, 2, 4, 8, 16
 
 EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "fv_encode",
                     "fv_encode_batch", "fv_kernel_timing", "fv_kernel_timing_read",
-                    "fv_strerror", "fv_last_device_error")
+                    "fv_server_config_default", "fv_server_create", "fv_server_destroy",
+                    "fv_server_submit", "fv_server_poll", "fv_server_next_done",
+                    "fv_server_get_stats", "fv_strerror", "fv_last_device_error")
+EXEC_HIP, EXEC_FAKE = 0, 1
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("precision", ctypes.c_int),
+                ("flags", ctypes.c_uint), ("max_queue", ctypes.c_int), ("n_streams", ctypes.c_int),
+                ("max_batch_frames", ctypes.c_int), ("max_batch_rows", ctypes.c_int64),
+                ("deadline_ms", ctypes.c_double), ("executor", ctypes.c_int),
+                ("fake_K", ctypes.c_int), ("fake_D", ctypes.c_int),
+                ("fake_us_per_krow", ctypes.c_double), ("fake_fail_every", ctypes.c_int)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("t_submit_us", ctypes.c_double), ("t_admit_us", ctypes.c_double),
+                ("t_start_us", ctypes.c_double), ("t_done_us", ctypes.c_double),
+                ("rows", ctypes.c_int64), ("batch_frames", ctypes.c_int), ("status", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("rows_done", ctypes.c_int64),
+                ("queued", ctypes.c_int), ("in_flight", ctypes.c_int),
+                ("admitted_bytes", ctypes.c_size_t), ("peak_admitted_bytes", ctypes.c_size_t),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("busy_s", ctypes.c_double)]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfv.so")
@@ -57,6 +85,17 @@ def load():
     lib.fv_encode_batch.argtypes = [vp, vp, vp, i32, vp, i32, u32, vp]
     lib.fv_kernel_timing.argtypes = [i32]
     lib.fv_kernel_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.fv_server_config_default.argtypes = [ctypes.POINTER(ServerConfig)]
+    lib.fv_server_config_default.restype = None
+    lib.fv_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.fv_server_destroy.argtypes = [vp]
+    lib.fv_server_submit.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.fv_server_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(ReqStats)]
+    lib.fv_server_next_done.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
+    lib.fv_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats), i32]
+    for f in (lib.fv_server_create, lib.fv_server_destroy, lib.fv_server_submit,
+              lib.fv_server_poll, lib.fv_server_next_done, lib.fv_server_get_stats):
+        f.restype = i32
     lib.fv_strerror.argtypes = [i32]
     lib.fv_strerror.restype = ctypes.c_char_p
     lib.fv_last_device_error.argtypes = []
@@ -244,3 +283,89 @@ def encode_batch(g: Gmm, X, offsets, out=None, precision: int = PREC_FP32, flags
                                 int(precision), f, ctypes.c_void_p(s))
     _check(rc, "fv_encode_batch")
     return out
+
+
+def server_config(**kw) -> ServerConfig:
+    """fv_server_config_default(), then the given fields."""
+    c = ServerConfig()
+    load().fv_server_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+class Server:
+    """Owning wrapper of an ``fv_server*`` (continuous-batching encoder)."""
+
+    def __init__(self, g: Gmm | None, cfg: ServerConfig, out_len: int | None = None, D: int | None = None):
+        h = ctypes.c_void_p()
+        _check(load().fv_server_create(ctypes.c_void_p(g.handle) if g else None, ctypes.byref(cfg),
+                                       ctypes.byref(h)), "fv_server_create")
+        self.handle = h.value
+        self.gmm = g
+        self.out_len = g.out_len if g else 2 * cfg.fake_K * cfg.fake_D
+        self.D = g.D if g else cfg.fake_D
+
+    def submit(self, X) -> int:
+        Xn = _host_f32(X)
+        if Xn.ndim != 2 or Xn.shape[1] != self.D:
+            raise ValueError("X must be [N, D]")
+        t = ctypes.c_uint64()
+        rc = load().fv_server_submit(ctypes.c_void_p(self.handle), ctypes.c_void_p(Xn.ctypes.data),
+                                     int(Xn.shape[0]), ctypes.byref(t))
+        if rc != OK:
+            raise FvError(rc, "fv_server_submit")
+        return t.value
+
+    def try_submit(self, X):
+        """(code, ticket or None) without raising."""
+        Xn = _host_f32(X)
+        t = ctypes.c_uint64()
+        rc = load().fv_server_submit(ctypes.c_void_p(self.handle), ctypes.c_void_p(Xn.ctypes.data),
+                                     int(Xn.shape[0]), ctypes.byref(t))
+        return rc, (t.value if rc == OK else None)
+
+    def poll(self, ticket: int, want_out: bool = True):
+        """(code, out or None, stats dict or None)."""
+        out = np.empty(self.out_len, np.float32) if want_out else None
+        st = ReqStats()
+        rc = load().fv_server_poll(ctypes.c_void_p(self.handle), ctypes.c_uint64(ticket),
+                                   ctypes.c_void_p(out.ctypes.data) if want_out else None,
+                                   ctypes.byref(st))
+        if rc == PENDING or rc == E_NOTFOUND:
+            return rc, None, None
+        stats = {f: getattr(st, f) for f, _ in ReqStats._fields_}
+        return rc, (out if rc == OK else None), stats
+
+    def next_done(self, timeout_ms: float = -1.0):
+        t = ctypes.c_uint64()
+        rc = load().fv_server_next_done(ctypes.c_void_p(self.handle), float(timeout_ms), ctypes.byref(t))
+        if rc == PENDING:
+            return None
+        _check(rc, "fv_server_next_done")
+        return t.value
+
+    def stats(self, reset: bool = False) -> dict:
+        st = ServerStats()
+        _check(load().fv_server_get_stats(ctypes.c_void_p(self.handle), ctypes.byref(st), int(reset)),
+               "fv_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(load().fv_server_destroy(ctypes.c_void_p(self.handle)), "fv_server_destroy")
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.fv_server_destroy(ctypes.c_void_p(self.handle))
+                self.handle = 0
+        except Exception:
+            pass

@@ -1,0 +1,106 @@
+"""Serving loop on the GPU: results against the FP64 oracle, bitwise equality of a frame
+served alone and inside a mix, and budget-forced queueing."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import fvsynth
+import oracle
+from oracle.metrics import errors
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1604_03498_amd as fvmod
+    fvmod.load()
+    return fvmod
+
+
+def drain(s, tickets, timeout=60.0):
+    res, pending, t0 = {}, set(tickets), time.time()
+    while pending and time.time() - t0 < timeout:
+        t = s.next_done(200.0)
+        if t is None or t not in pending:
+            continue
+        res[t] = s.poll(t)
+        pending.discard(t)
+    assert not pending, f"{len(pending)} requests never finished"
+    return res
+
+
+def test_server_results_match_oracle_and_batch(fv):
+    say("[gpu] server fp32 K=256 D=64")
+    g = fvsynth.gmm(256, 64, 0)
+    sizes = [3000, 17, 8000, 0, 1200, 9001]
+    frames = [fvsynth.frame(g, n, 500 + i, 0.05) for i, n in enumerate(sizes)]
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    with fv.Server(h, fv.server_config(precision=fv.PREC_FP32, n_streams=2)) as s:
+        tickets = [s.submit(X) for X in frames]
+        res = drain(s, tickets)
+    X, off = np.concatenate(frames), np.cumsum([0] + sizes)
+    batch = fv.encode_batch(h, X, off)
+    for i, t in enumerate(tickets):
+        rc, out, st = res[t]
+        assert rc == fv.OK, rc
+        assert np.array_equal(out, batch[i]), f"frame {i} differs from the batched encode"
+        if sizes[i] == 0:
+            assert np.all(out == 0)
+            continue
+        e = errors(out, oracle.encode_gmm(frames[i], g))
+        say(f"  frame {i} N={sizes[i]} frames-in-launch={st['batch_frames']} e_inf={e['e_inf']:.2e}")
+        assert e["e_inf"] <= 1e-5 and e["e_2"] <= 1e-5
+
+
+@pytest.mark.parametrize("K,D,prec", [(256, 64, 0), (512, 80, 1)])
+def test_alone_equals_mix_bitwise(fv, K, D, prec):
+    say(f"[gpu] server alone vs mix K={K} D={D} precision={prec}")
+    g = fvsynth.gmm(K, D, 0)
+    target = fvsynth.frame(g, 12500, 77, 0.05)
+    others = [fvsynth.frame(g, n, 900 + i, 0.05) for i, n in enumerate([8000, 3000, 18000, 500, 9999])]
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    with fv.Server(h, fv.server_config(precision=prec, n_streams=3)) as s:
+        t = s.submit(target)
+        alone = drain(s, [t])[t]
+        ts = [s.submit(o) for o in others[:3]] + [s.submit(target)] + [s.submit(o) for o in others[3:]]
+        res = drain(s, ts)
+    mixed = res[ts[3]]
+    assert alone[0] == fv.OK and mixed[0] == fv.OK
+    say(f"  alone launch frames={alone[2]['batch_frames']}, mixed launch frames={mixed[2]['batch_frames']}")
+    assert np.array_equal(alone[1], mixed[1])
+    e = errors(alone[1], oracle.encode_gmm(target, g))
+    say(f"  vs oracle: {e}")
+    tol = 1e-5 if prec == 0 else 1e-3
+    assert e["e_inf"] <= tol and e["e_2"] <= tol
+
+
+def test_small_budget_forces_queueing(fv):
+    say("[gpu] server small budget")
+    g = fvsynth.gmm(64, 32, 3)
+    frames = [fvsynth.frame(g, 4000, 40 + i, 0.05) for i in range(8)]
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    # footprint of one 4000-row frame, measured by probing: a budget of about 1.5 frames
+    with fv.Server(h, fv.server_config(n_streams=4)) as probe:
+        t = probe.submit(frames[0])
+        drain(probe, [t])
+        per = probe.stats()["peak_admitted_bytes"]
+    with fv.Server(h, fv.server_config(n_streams=4, hbm_budget_bytes=int(per * 1.5))) as s:
+        tickets = [s.submit(X) for X in frames]
+        res = drain(s, tickets)
+        st = s.stats()
+    assert st["peak_admitted_bytes"] <= int(per * 1.5)
+    for i, t in enumerate(tickets):
+        rc, out, _ = res[t]
+        assert rc == fv.OK
+        e = errors(out, oracle.encode_gmm(frames[i], g))
+        assert e["e_inf"] <= 1e-5 and e["e_2"] <= 1e-5
