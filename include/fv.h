@@ -114,6 +114,25 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
                     int precision, unsigned flags, void* hip_stream);
 
 /*
+ * Launch tuning of one handle (set by an autotuner; the defaults are automatic choices).
+ *   batch_chunk         rows per frame-relative chunk in fv_encode_batch (rounded down to a
+ *                       multiple of 128; 0 = 1024).  Changing it changes the summation order
+ *                       of the batched path (results agree within rounding, not bitwise).
+ *   batch_path          0 = automatic (fused single pass when K <= 256), 1 = fused, 2 = two-pass
+ *   single_split_below  fv_encode takes the two-pass path for N below this (0 = automatic:
+ *                       four 32-row tiles per resident workgroup)
+ * Not synchronised with encodes running concurrently on the same handle.  Errors: FV_E_INVAL.
+ */
+typedef struct fv_tuning {
+  int batch_chunk;
+  int batch_path;
+  int64_t single_split_below;
+} fv_tuning;
+
+int fv_gmm_set_tuning(fv_gmm* gmm, const fv_tuning* tuning); /* NULL restores the defaults */
+int fv_gmm_get_tuning(const fv_gmm* gmm, fv_tuning* tuning);
+
+/*
  * Kernel timing (instrumentation for benchmarks and profilers).  fv_kernel_timing(1) resets
  * the counters and starts bracketing every launch of libfv's kernels with HIP events on the
  * stream the kernel is launched on; fv_kernel_timing(0) stops.  fv_kernel_timing_read waits

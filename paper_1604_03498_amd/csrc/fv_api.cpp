@@ -71,6 +71,31 @@ int device_cu_count(int device) {
 // Device scratch (partials, tables, staging) and pinned host staging, cached per (device,
 // stream).  Work on one stream is ordered, so reusing the buffers between calls is safe; a
 // buffer is only replaced after the stream has drained.
+// Everything a captured launch sequence bakes in: a replay is valid only for an equal key.
+struct GraphKey {
+  int kind = 0;  // 0 = fv_encode, 1 = fv_encode_batch
+  const fv_gmm* gmm = nullptr;
+  int precision = 0;
+  unsigned flags = 0;
+  int path = 0, P = 0;
+  int64_t rows = 0;
+  int B = 0, n_items = 0, n_groups = 0;
+  const void* X = nullptr;
+  const void* out = nullptr;
+  const void* dev = nullptr;
+  const void* pinned = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return kind == o.kind && gmm == o.gmm && precision == o.precision && flags == o.flags &&
+           path == o.path && P == o.P && rows == o.rows && B == o.B && n_items == o.n_items &&
+           n_groups == o.n_groups && X == o.X && out == o.out && dev == o.dev && pinned == o.pinned;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct Workspace {
   std::mutex mu;
   char* dev = nullptr;
@@ -79,7 +104,57 @@ struct Workspace {
   size_t pin_cap = 0;
   hipEvent_t pin_done = nullptr;  // last H2D copy out of `pinned`
   bool pin_pending = false;
+  std::vector<GraphEntry> graphs;  // most recent last
 };
+
+constexpr size_t kMaxGraphs = 8;
+
+void drop_graphs(Workspace* ws) {
+  for (auto& g : ws->graphs) (void)hipGraphExecDestroy(g.exec);
+  ws->graphs.clear();
+}
+
+// Graph replay of launch sequences: on for device-resident inputs and outputs on a non-null
+// stream, unless FV_GRAPH=0 or kernel timing is on.
+bool graphs_enabled() {
+  const char* e = std::getenv("FV_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+// Runs `enqueue` on stream s directly, or replays (capturing on first use) a graph cached
+// under `key` in the workspace.
+template <class F>
+int run_sequence(Workspace* ws, const GraphKey& key, bool use_graph, hipStream_t s, F&& enqueue) {
+  if (!use_graph) return enqueue();
+  for (size_t i = 0; i < ws->graphs.size(); ++i)
+    if (ws->graphs[i].key == key) {
+      GraphEntry e = ws->graphs[i];
+      ws->graphs.erase(ws->graphs.begin() + (long)i);
+      ws->graphs.push_back(e);
+      FV_HIP(hipGraphLaunch(e.exec, s));
+      return FV_OK;
+    }
+  FV_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue();
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s, &g);
+  if (rc != FV_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (ec != hipSuccess) return hip_fail(ec);
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return hip_fail(ei);
+  if (ws->graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(ws->graphs.front().exec);
+    ws->graphs.erase(ws->graphs.begin());
+  }
+  ws->graphs.push_back(GraphEntry{key, ex});
+  FV_HIP(hipGraphLaunch(ex, s));
+  return FV_OK;
+}
 
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
@@ -95,6 +170,7 @@ int ensure_dev(Workspace* ws, size_t need, hipStream_t s) {
   if (need <= ws->dev_cap) return FV_OK;
   if (ws->dev) {
     FV_HIP(hipStreamSynchronize(s));
+    drop_graphs(ws);
     FV_HIP(hipFree(ws->dev));
     ws->dev = nullptr;
     ws->dev_cap = 0;
@@ -114,6 +190,7 @@ int ensure_pinned(Workspace* ws, size_t need) {
   if (!ws->pin_done) FV_HIP(hipEventCreateWithFlags(&ws->pin_done, hipEventDisableTiming));
   if (need <= ws->pin_cap) return FV_OK;
   if (ws->pinned) {
+    drop_graphs(ws);
     FV_HIP(hipHostFree(ws->pinned));
     ws->pinned = nullptr;
     ws->pin_cap = 0;
@@ -217,17 +294,24 @@ int resident_fused(int device, int Wg) { return device_cu_count(device) * std::m
 // Single frame: the fused kernel needs several 32-row tiles per resident workgroup to amortise
 // its per-chunk partial write; below that the two-pass path (more, smaller workgroups and
 // fewer partial slots) is used.  More than 256 components always take the two-pass path.
-Path choose_single(const fv::Consts& c, int64_t N, int device) {
+Path choose_single(const fv_gmm* g, int64_t N) {
+  const fv::Consts& c = g->c;
   if (c.Kp > fv::kFusedMaxK) return Path::kSplit;
   const int o = path_override();
   if (o == 1) return Path::kFused;
   if (o == 2) return Path::kSplit;
-  return N < (int64_t)4 * fv::kTile * resident_fused(device, c.Wg) ? Path::kSplit : Path::kFused;
+  const int64_t below = g->single_split_below > 0
+                            ? g->single_split_below
+                            : (int64_t)4 * fv::kTile * resident_fused(g->device, c.Wg);
+  return N < below ? Path::kSplit : Path::kFused;
 }
 
-Path choose_batch(const fv::Consts& c) {
-  if (c.Kp > fv::kFusedMaxK) return Path::kSplit;
-  return path_override() == 2 ? Path::kSplit : Path::kFused;
+Path choose_batch(const fv_gmm* g) {
+  if (g->c.Kp > fv::kFusedMaxK) return Path::kSplit;
+  const int o = path_override();
+  if (o == 1) return Path::kFused;
+  if (o == 2) return Path::kSplit;
+  return g->batch_path == 2 ? Path::kSplit : Path::kFused;
 }
 
 // Chunk length of the fused kernel for a single frame: enough items to give every resident
@@ -248,17 +332,15 @@ int split_single_chunk(int64_t N, int device, int slices, int round) {
   return (int)std::min<int64_t>(P, (int64_t)1 << 20);
 }
 
-// Frame-relative chunk length of the batched path (a multiple of 128 rows).
-int batch_chunk() {
-  static int P = [] {
-    int v = 1024;
-    if (const char* e = std::getenv("FV_BATCH_CHUNK")) {
-      int x = std::atoi(e);
-      if (x >= 128) v = (x / 128) * 128;
-    }
-    return v;
-  }();
-  return P;
+// Frame-relative chunk length of the batched path (a multiple of 128 rows): FV_BATCH_CHUNK
+// (test override), else the handle's tuning, else 1024.
+int batch_chunk(const fv_gmm* g) {
+  if (const char* e = std::getenv("FV_BATCH_CHUNK")) {
+    const int x = std::atoi(e);
+    if (x >= 128) return (x / 128) * 128;
+  }
+  if (g->batch_chunk >= 128) return (g->batch_chunk / 128) * 128;
+  return 1024;
 }
 
 // ---- optional kernel timing: event pairs recorded around launches on the launch stream
@@ -281,6 +363,11 @@ hipEvent_t timing_event() {
   }
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
+}
+
+bool timing_enabled() {
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  return g_timing.enabled;
 }
 
 // Records a start event when timing is on; returns it (or null).
@@ -310,9 +397,10 @@ void timing_end(hipEvent_t start, int which, hipStream_t s) {
 }  // namespace
 
 namespace fv {
-size_t batch_device_bytes(const Consts& c, const int64_t* sizes, int B) {
-  const bool split = choose_batch(c) == Path::kSplit;
-  const int P = batch_chunk();
+size_t batch_device_bytes(const fv_gmm* g, const int64_t* sizes, int B) {
+  const Consts& c = g->c;
+  const bool split = choose_batch(g) == Path::kSplit;
+  const int P = batch_chunk(g);
   int64_t rows = 0, items = 0, groups = 0;
   for (int b = 0; b < B; ++b) {
     const int64_t ni = (sizes[b] + P - 1) / P;
@@ -538,6 +626,31 @@ int fv_gmm_free(fv_gmm* gmm) {
   return rc;
 }
 
+int fv_gmm_set_tuning(fv_gmm* gmm, const fv_tuning* t) {
+  if (!gmm) return FV_E_INVAL;
+  if (!t) {
+    gmm->batch_chunk = 0;
+    gmm->batch_path = 0;
+    gmm->single_split_below = 0;
+    return FV_OK;
+  }
+  if (t->batch_chunk < 0 || (t->batch_chunk > 0 && t->batch_chunk < 128) || t->batch_path < 0 ||
+      t->batch_path > 2 || t->single_split_below < 0)
+    return FV_E_INVAL;
+  gmm->batch_chunk = t->batch_chunk;
+  gmm->batch_path = t->batch_path;
+  gmm->single_split_below = t->single_split_below;
+  return FV_OK;
+}
+
+int fv_gmm_get_tuning(const fv_gmm* gmm, fv_tuning* t) {
+  if (!gmm || !t) return FV_E_INVAL;
+  t->batch_chunk = gmm->batch_chunk;
+  t->batch_path = gmm->batch_path;
+  t->single_split_below = gmm->single_split_below;
+  return FV_OK;
+}
+
 int fv_gmm_info(const fv_gmm* gmm, int* K, int* D, int* device) {
   if (!gmm) return FV_E_INVAL;
   if (K) *K = gmm->K;
@@ -560,7 +673,7 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   if (!ws) return FV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ws->mu);
 
-  const Path path = choose_single(c, N, gmm->device);
+  const Path path = choose_single(gmm, N);
   const int slices = c.Kp / fv::kCompsPerWave;
   int P = fv::kTile;
   if (N > 0)
@@ -596,23 +709,43 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   float* Od = (flags & FV_OUT_DEVICE) ? out : odev;
   const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
 
-  if (n_items > 0) {
-    hipEvent_t t0 = timing_begin(s);
-    if (path == Path::kFused) {
-      FV_HIP(run_stats(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
-    } else {
-      const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
-      const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
-      FV_HIP(run_lse(c, precision, Xd, vec_ok, N, n_tiles, grid1, lse, N, s));
-      FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, lse, N, partials, s));
+  auto enqueue = [&]() -> int {
+    if (n_items > 0) {
+      hipEvent_t t0 = timing_begin(s);
+      if (path == Path::kFused) {
+        FV_HIP(run_stats(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
+      } else {
+        const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
+        const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
+        FV_HIP(run_lse(c, precision, Xd, vec_ok, N, n_tiles, grid1, lse, N, s));
+        FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, lse, N, partials, s));
+      }
+      timing_end(t0, 0, s);
     }
-    timing_end(t0, 0, s);
-  }
-  fv::Frame single{N, 0, n_items, 0, n_groups};
-  hipEvent_t t1 = timing_begin(s);
-  FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, nullptr, n_groups, flags, Od, gbuf,
-                             normpart, s));
-  timing_end(t1, 1, s);
+    fv::Frame single{N, 0, n_items, 0, n_groups};
+    hipEvent_t t1 = timing_begin(s);
+    FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, nullptr, n_groups, flags, Od, gbuf,
+                               normpart, s));
+    timing_end(t1, 1, s);
+    return FV_OK;
+  };
+  const bool use_graph = graphs_enabled() && s != nullptr && (flags & FV_X_DEVICE) &&
+                         (flags & FV_OUT_DEVICE) && !timing_enabled();
+  GraphKey key;
+  key.kind = 0;
+  key.gmm = gmm;
+  key.precision = precision;
+  key.flags = flags & (FV_NO_POWER_NORM | FV_NO_L2_NORM);
+  key.path = (int)path;
+  key.P = P;
+  key.rows = N;
+  key.n_items = n_items;
+  key.n_groups = n_groups;
+  key.X = Xd;
+  key.out = Od;
+  key.dev = ws->dev;
+  rc = run_sequence(ws, key, use_graph, s, enqueue);
+  if (rc) return rc;
   if (!(flags & FV_OUT_DEVICE))
     FV_HIP(hipMemcpyAsync(out, Od, out_len * 4, hipMemcpyDeviceToHost, s));
   if (!(flags & FV_ASYNC)) FV_HIP(hipStreamSynchronize(s));
@@ -634,8 +767,8 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   if (rows > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
 
   // Frame-relative chunking: frame b's chunk j covers its rows [j*P, (j+1)*P).
-  const Path path = choose_batch(c);
-  const int P = batch_chunk();
+  const Path path = choose_batch(gmm);
+  const int P = batch_chunk(gmm);
   std::vector<fv::Frame> frames((size_t)B);
   int64_t n_items64 = 0, n_groups64 = 0;
   for (int b = 0; b < B; ++b) {
@@ -706,10 +839,6 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
       }
     }
   }
-  FV_HIP(hipMemcpyAsync(dframes, ws->pinned, b_tab, hipMemcpyHostToDevice, s));
-  FV_HIP(hipEventRecord(ws->pin_done, s));
-  ws->pin_pending = true;
-
   const float* Xd = X;
   if (!(flags & FV_X_DEVICE) && rows > 0) {
     FV_HIP(hipMemcpyAsync(xdev, X, (size_t)rows * c.D * 4, hipMemcpyHostToDevice, s));
@@ -718,25 +847,52 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
   float* Od = (flags & FV_OUT_DEVICE) ? out : odev;
   const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
-  if (n_items > 0) {
-    hipEvent_t t0 = timing_begin(s);
-    if (path == Path::kFused) {
-      const int grid = std::max(1, std::min(n_items, resident_fused(gmm->device, c.Wg)));
-      FV_HIP(run_stats(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid, partials, s));
-    } else {
-      const int n_tiles = (int)((rows + fv::kTile - 1) / fv::kTile);
-      const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
-      FV_HIP(run_lse(c, precision, Xd, vec_ok, rows, n_tiles, grid1, lse, rows, s));
-      const int slices = c.Kp / fv::kCompsPerWave;
-      const int grid2 = std::max(1, std::min(n_items, 2 * device_cu_count(gmm->device) / slices + 1));
-      FV_HIP(run_sliced(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
+  // One persistent statistics launch over the work table (grid = resident workgroups), then
+  // the finalize; the table copy from pinned memory is part of the sequence.
+  auto enqueue = [&]() -> int {
+    FV_HIP(hipMemcpyAsync(dframes, ws->pinned, b_tab, hipMemcpyHostToDevice, s));
+    if (n_items > 0) {
+      hipEvent_t t0 = timing_begin(s);
+      if (path == Path::kFused) {
+        const int grid = std::max(1, std::min(n_items, resident_fused(gmm->device, c.Wg)));
+        FV_HIP(run_stats(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid, partials, s));
+      } else {
+        const int n_tiles = (int)((rows + fv::kTile - 1) / fv::kTile);
+        const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
+        FV_HIP(run_lse(c, precision, Xd, vec_ok, rows, n_tiles, grid1, lse, rows, s));
+        const int slices = c.Kp / fv::kCompsPerWave;
+        const int grid2 = std::max(1, std::min(n_items, 2 * device_cu_count(gmm->device) / slices + 1));
+        FV_HIP(run_sliced(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
+      }
+      timing_end(t0, 0, s);
     }
-    timing_end(t0, 0, s);
-  }
-  hipEvent_t t1 = timing_begin(s);
-  FV_HIP(fv::launch_finalize(c, partials, dframes, fv::Frame{0, 0, 0, 0, 0}, B, dgroups, n_groups,
-                             flags, Od, gbuf, normpart, s));
-  timing_end(t1, 1, s);
+    hipEvent_t t1 = timing_begin(s);
+    FV_HIP(fv::launch_finalize(c, partials, dframes, fv::Frame{0, 0, 0, 0, 0}, B, dgroups, n_groups,
+                               flags, Od, gbuf, normpart, s));
+    timing_end(t1, 1, s);
+    return FV_OK;
+  };
+  const bool use_graph = graphs_enabled() && s != nullptr && (flags & FV_X_DEVICE) &&
+                         (flags & FV_OUT_DEVICE) && !timing_enabled();
+  GraphKey key;
+  key.kind = 1;
+  key.gmm = gmm;
+  key.precision = precision;
+  key.flags = flags & (FV_NO_POWER_NORM | FV_NO_L2_NORM);
+  key.path = (int)path;
+  key.P = P;
+  key.rows = rows;
+  key.B = B;
+  key.n_items = n_items;
+  key.n_groups = n_groups;
+  key.X = Xd;
+  key.out = Od;
+  key.dev = ws->dev;
+  key.pinned = ws->pinned;
+  rc = run_sequence(ws, key, use_graph, s, enqueue);
+  if (rc) return rc;
+  FV_HIP(hipEventRecord(ws->pin_done, s));
+  ws->pin_pending = true;
   if (!(flags & FV_OUT_DEVICE))
     FV_HIP(hipMemcpyAsync(out, Od, (size_t)B * out_len * 4, hipMemcpyDeviceToHost, s));
   if (!(flags & FV_ASYNC)) FV_HIP(hipStreamSynchronize(s));

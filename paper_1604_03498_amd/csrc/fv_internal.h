@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct fv_gmm;
+
 namespace fv {
 
 constexpr int kTile = 32;        // descriptors per tile (one 32x32 MFMA block of rows)
@@ -107,7 +109,7 @@ int finalize_blocks(const Consts& c);
 
 // Device bytes one fv_encode_batch call needs for frames of the given sizes (workspace plus
 // device-resident X and out), used by the server's admission control.
-size_t batch_device_bytes(const Consts& c, const int64_t* sizes, int B);
+size_t batch_device_bytes(const struct ::fv_gmm* g, const int64_t* sizes, int B);
 
 // ---- 16-bit operand forms (one translation unit per form) --------------------------------
 struct Frags16 {
@@ -140,4 +142,8 @@ struct fv_gmm {
   int K = 0, D = 0, device = 0;
   fv::Consts c{};
   void* dev_block = nullptr;  // one allocation holding every constant array
+  // launch tuning (0 = automatic)
+  int batch_chunk = 0;
+  int batch_path = 0;
+  int64_t single_split_below = 0;
 };

@@ -18,11 +18,16 @@ PREC_FP32, PREC_BF16_SPLIT, PREC_FP16_SPLIT, PREC_BF16 = 0, 1, 2, 3
 X_DEVICE, OUT_DEVICE, NO_POWER_NORM, NO_L2_NORM, ASYNC = 1, 2, 4, 8, 16
 
 EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "fv_encode",
-                    "fv_encode_batch", "fv_kernel_timing", "fv_kernel_timing_read",
-                    "fv_server_config_default", "fv_server_create", "fv_server_destroy",
+                    "fv_encode_batch", "fv_gmm_set_tuning", "fv_gmm_get_tuning",
+                    "fv_kernel_timing", "fv_kernel_timing_read", "fv_server_config_default", "fv_server_create", "fv_server_destroy",
                     "fv_server_submit", "fv_server_poll", "fv_server_next_done",
                     "fv_server_get_stats", "fv_strerror", "fv_last_device_error")
 EXEC_HIP, EXEC_FAKE = 0, 1
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("batch_chunk", ctypes.c_int), ("batch_path", ctypes.c_int),
+                ("single_split_below", ctypes.c_int64)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -83,6 +88,10 @@ def load():
     lib.fv_gmm_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.fv_encode.argtypes = [vp, vp, i64, vp, i32, u32, vp]
     lib.fv_encode_batch.argtypes = [vp, vp, vp, i32, vp, i32, u32, vp]
+    lib.fv_gmm_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.fv_gmm_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.fv_gmm_set_tuning.restype = i32
+    lib.fv_gmm_get_tuning.restype = i32
     lib.fv_kernel_timing.argtypes = [i32]
     lib.fv_kernel_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     lib.fv_server_config_default.argtypes = [ctypes.POINTER(ServerConfig)]
@@ -193,6 +202,19 @@ def gmm_info(g: Gmm):
     _check(load().fv_gmm_info(ctypes.c_void_p(g.handle), ctypes.byref(K), ctypes.byref(D),
                               ctypes.byref(dev)), "fv_gmm_info")
     return K.value, D.value, dev.value
+
+
+def set_tuning(g: Gmm, batch_chunk: int = 0, batch_path: int = 0, single_split_below: int = 0):
+    """fv_gmm_set_tuning (all zero = automatic)."""
+    t = Tuning(int(batch_chunk), int(batch_path), int(single_split_below))
+    _check(load().fv_gmm_set_tuning(ctypes.c_void_p(g.handle), ctypes.byref(t)), "fv_gmm_set_tuning")
+
+
+def get_tuning(g: Gmm) -> dict:
+    t = Tuning()
+    _check(load().fv_gmm_get_tuning(ctypes.c_void_p(g.handle), ctypes.byref(t)), "fv_gmm_get_tuning")
+    return {"batch_chunk": t.batch_chunk, "batch_path": t.batch_path,
+            "single_split_below": t.single_split_below}
 
 
 def _is_torch(x) -> bool:

@@ -1,0 +1,102 @@
+"""Graph capture and replay of the launch sequences (device-resident X and out on a stream):
+every replay, with eager work and synchronisation in between, must equal the direct
+(uncaptured) encode bitwise, including when the input data or the batch table change."""
+import sys
+
+import numpy as np
+import pytest
+
+import fvsynth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1604_03498_amd as fvmod
+    fvmod.load()
+    return fvmod
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_single_frame_replays(fv, prec, monkeypatch):
+    import torch
+    say(f"[gpu] graph single frame precision={prec}")
+    g = fvsynth.gmm(256, 64, 0)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    frames = [fvsynth.frame(g, 8000, 100 + i, 0.05) for i in range(3)]
+    stream = torch.cuda.Stream()
+    Xd = torch.empty(8000, 64, device="cuda")
+    out = torch.empty(2 * 256 * 64, device="cuda")
+    monkeypatch.setenv("FV_GRAPH", "0")
+    direct = []
+    for X in frames:
+        Xd.copy_(torch.from_numpy(X))
+        direct.append(fv.encode(h, Xd, out=out.clone(), precision=prec, stream=stream).cpu().numpy())
+    monkeypatch.setenv("FV_GRAPH", "1")
+    for rep in range(3):
+        for i, X in enumerate(frames):
+            Xd.copy_(torch.from_numpy(X))          # same pointer, new contents
+            torch.cuda.synchronize()
+            fv.encode(h, Xd, out=out, precision=prec, flags=fv.ASYNC, stream=stream)
+            stream.synchronize()
+            got = out.cpu().numpy()
+            _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+            assert np.array_equal(got, direct[i]), (rep, i)
+
+
+def test_batch_replays_with_new_table(fv, monkeypatch):
+    import torch
+    say("[gpu] graph batch")
+    g = fvsynth.gmm(256, 64, 0)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    shapes = [[1000, 3000, 500], [2000, 2000, 500], [3000, 1000, 500]]   # same items and groups
+    data = [fvsynth.batch_frames(g, s, seed0=10 * i) for i, s in enumerate(shapes)]
+    stream = torch.cuda.Stream()
+    Xd = torch.empty(4500, 64, device="cuda")
+    out = torch.empty(3, 2 * 256 * 64, device="cuda")
+    monkeypatch.setenv("FV_GRAPH", "0")
+    direct = []
+    for X, off in data:
+        Xd.copy_(torch.from_numpy(X))
+        direct.append(fv.encode_batch(h, Xd, off, out=out.clone(), stream=stream).cpu().numpy())
+    monkeypatch.setenv("FV_GRAPH", "1")
+    for rep in range(3):
+        for i, (X, off) in enumerate(data):
+            Xd.copy_(torch.from_numpy(X))
+            torch.cuda.synchronize()
+            fv.encode_batch(h, Xd, off, out=out, flags=fv.ASYNC, stream=stream)
+            stream.synchronize()
+            assert np.array_equal(out.cpu().numpy(), direct[i]), (rep, i)
+
+
+def test_autotuner_keeps_results_within_tolerance(fv, tmp_path, monkeypatch):
+    import torch
+    import oracle
+    from oracle.metrics import errors
+    from paper_1604_03498_amd import autotune
+    monkeypatch.setenv("FV_TUNE_CACHE", str(tmp_path / "tune.json"))
+    say("[gpu] autotuner")
+    g = fvsynth.gmm(256, 64, 0)
+    X, off = fvsynth.batch_frames(g, [5000, 2500, 9000], seed0=70)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    Xd = torch.from_numpy(X).cuda()
+    cfg = autotune.tune_batch(h, Xd, off, 0, chunks=(512, 2048), reps=2)
+    say(f"  chosen {cfg['batch_path']}/{cfg['batch_chunk']} from {[(t['batch_path'], t['batch_chunk'], round(t['ms'], 3)) for t in cfg['trials']]}")
+    assert not cfg["cached"] and len(cfg["trials"]) == 4
+    assert fv.get_tuning(h)["batch_chunk"] == cfg["batch_chunk"]
+    got = fv.encode_batch(h, Xd, off).cpu().numpy()
+    ref = oracle.encode_batch(X, off, g.weights, g.means, g.variances)
+    for b in range(3):
+        e = errors(got[b], ref[b])
+        assert e["e_inf"] <= 1e-5 and e["e_2"] <= 1e-5
+    h2 = fv.gmm_load(g.weights, g.means, g.variances)
+    assert autotune.apply(h2, 0, int(off[-1]))
+    assert fv.get_tuning(h2) == fv.get_tuning(h)

@@ -72,7 +72,7 @@ def test_budget_limits_in_flight_bytes_and_rejects_oversized():
 
 
 def test_queue_full_returns_again():
-    with fake(max_queue=3, n_streams=1, fake_us_per_krow=1e6) as s:
+    with fake(max_queue=3, n_streams=1, max_batch_frames=1, fake_us_per_krow=1e6) as s:
         codes = [s.try_submit(np.zeros((1000, D), np.float32))[0] for _ in range(8)]
         assert fv.E_AGAIN in codes
         assert codes.count(fv.OK) <= 4               # one running + three queued
