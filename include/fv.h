@@ -168,6 +168,8 @@ typedef struct fv_server_config {
   int64_t max_batch_rows;   /* rows per launch (<= 0: 262144) */
   double deadline_ms;       /* a request not admitted within this time fails with
                                FV_E_TIMEOUT (<= 0: no deadline) */
+  double batch_window_us;   /* a launch that is not yet full waits until its oldest request is
+                               this old, to collect more frames (<= 0: launch at once) */
   int executor;             /* FV_EXEC_HIP or FV_EXEC_FAKE */
   int fake_K, fake_D;       /* FV_EXEC_FAKE only: output size 2*K*D when gmm is NULL */
   double fake_us_per_krow;  /* FV_EXEC_FAKE only */

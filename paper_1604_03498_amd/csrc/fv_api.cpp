@@ -323,10 +323,11 @@ int fused_single_chunk(int64_t N, int device, int Wg) {
   return (int)std::min<int64_t>(per * fv::kTile, (int64_t)1 << 20);
 }
 
-// Chunk length of the second pass for a single frame: about two workgroups per CU over all
-// (chunk, slice) pairs, in whole rounds of the workgroup's four 32-row tiles.
-int split_single_chunk(int64_t N, int device, int slices, int round) {
-  const int64_t target_chunks = std::max<int64_t>(1, (2 * device_cu_count(device) + slices - 1) / slices);
+// Chunk length of the second pass for a single frame: one round of resident workgroups over all
+// (chunk, slice) pairs, in whole rounds of the workgroup's 32-row tiles.
+int split_single_chunk(int64_t N, int device, int slices, int round, int wgs_per_cu) {
+  const int64_t target_chunks =
+      std::max<int64_t>(1, ((int64_t)wgs_per_cu * device_cu_count(device) + slices - 1) / slices);
   const int64_t per = (N + target_chunks - 1) / target_chunks;
   const int64_t P = std::max<int64_t>(round, (per + round - 1) / round * round);
   return (int)std::min<int64_t>(P, (int64_t)1 << 20);
@@ -678,7 +679,8 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   int P = fv::kTile;
   if (N > 0)
     P = (path == Path::kFused) ? fused_single_chunk(N, gmm->device, c.Wg)
-                               : split_single_chunk(N, gmm->device, slices, sliced_round(c, precision));
+                               : split_single_chunk(N, gmm->device, slices, sliced_round(c, precision),
+                                                    precision == FV_PREC_FP32 ? 2 : 1);
   const int n_items = N > 0 ? (int)((N + P - 1) / P) : 0;
   const int n_groups = (n_items + fv::kGroupItems - 1) / fv::kGroupItems;
   const int G = fv::lse_groups(c);

@@ -49,8 +49,85 @@ __device__ __forceinline__ float allreduce32(float v, Op op) {
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+__device__ __forceinline__ float select_f(bool c, float a, float b) { return c ? a : b; }
+
+// Orders LDS writes of this wave before its later LDS reads (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Reduce-scatter of the 16 C-layout registers over the 32 lanes of a half-wave: lane j ends
+// with the reduction (over all 32 lanes) of register j >> 1, i.e. of row crow(j >> 1, h);
+// lanes 2r and 2r+1 hold the same, bit-identical value.  Five exchange stages halve the
+// register count each time (38 VALU instructions for all 16 rows, against 16 separate
+// all-reduces of 6 each):
+//   stage 1  lanes j ^ 16  v_permlane16_swap of register pairs (r, r+8)
+//   stage 2  lanes j ^ 8   DPP row_ror:8,          pairs (r, r+4)
+//   stage 3  lanes j ^ 7   DPP row_half_mirror,    pairs (r, r+2)
+//   stage 4  lanes j ^ 2   DPP quad_perm [2,3,0,1], pairs (r, r+1)
+//   stage 5  lanes j ^ 1   DPP quad_perm [1,0,3,2]
+// A lane keeps the half of each pair selected by its own lane bit, sends the other half, and
+// combines what it keeps with what its partner sent.  The partner sets of successive stages
+// are disjoint, so every register is combined over all 32 lanes exactly once.
+template <class Op>
+__device__ __forceinline__ float reduce_scatter16(const float (&v)[16], int j, Op op) {
+  float a[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[r]), __float_as_uint(v[r + 8]),
+                                              false, false);
+    a[r] = op(__uint_as_float(p[0]), __uint_as_float(p[1]));  // bit 4 = 0: reg r, else r + 8
+  }
+  const bool b3 = (j >> 3) & 1, b2 = (j >> 2) & 1, b1 = (j >> 1) & 1;
+  float b[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float keep = select_f(b3, a[r + 4], a[r]);
+    const float send = select_f(b3, a[r], a[r + 4]);
+    b[r] = op(keep, dpp<0x128>(send));  // row_ror:8
+  }
+  float c[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const float keep = select_f(b2, b[r + 2], b[r]);
+    const float send = select_f(b2, b[r], b[r + 2]);
+    c[r] = op(keep, dpp<0x141>(send));  // row_half_mirror
+  }
+  const float keep = select_f(b1, c[1], c[0]);
+  const float send = select_f(b1, c[0], c[1]);
+  float d = op(keep, dpp<0x4E>(send));  // quad_perm [2,3,0,1]
+  return op(d, dpp<0xB1>(d));           // quad_perm [1,0,3,2]
+}
+
 // Row of the 32-row tile held in register r of a lane in half h.
 __device__ __forceinline__ constexpr int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+// Soft assignment, wave-local part: for the tile's 32 rows and this wave's 32 components,
+// e = exp2((hi - m_w) + lo) with m_w the wave's row maximum; the row maxima and the row sums
+// of e are published to red_m[row], red_s[row] (this wave's slice of the exchange arrays).
+__device__ __forceinline__ void softmax_wave(const f32x16& hi, const f32x16& lo, f32x16& e,
+                                             float* red_m, float* red_s, int j, int h) {
+  float v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = hi[r];
+  const float mrow = reduce_scatter16(v, j, MaxOp());
+  if (!(j & 1)) red_m[crow(j >> 1, h)] = mrow;
+  wave_sync();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const f32x4 m = *reinterpret_cast<const f32x4*>(red_m + 8 * q + 4 * h);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int r = 4 * q + p;
+      e[r] = fast_exp2((hi[r] - m[p]) + lo[r]);
+      v[r] = e[r];
+    }
+  }
+  const float srow = reduce_scatter16(v, j, AddOp());
+  if (!(j & 1)) red_s[crow(j >> 1, h)] = srow;
+}
 
 // ---- descriptor tile staging ------------------------------------------------------------
 // Tile = 32 rows x DP features, fetched as float4 slots into registers by NT threads (thread
@@ -113,13 +190,14 @@ struct TileIO {
 template <int DP>
 __device__ __forceinline__ void estep_f32(const float* __restrict__ xr, const float (&areg)[DP],
                                           float cval, f32x16& hi, f32x16& lo) {
+  constexpr int CH = 16;  // MFMA steps per accumulation chain
 #pragma unroll
-  for (int ch = 0; ch < DP / 16; ++ch) {
+  for (int ch = 0; ch < DP / CH; ++ch) {
     f32x16 a;
 #pragma unroll
     for (int r = 0; r < 16; ++r) a[r] = (ch == 0) ? cval : 0.f;
 #pragma unroll
-    for (int s = 16 * ch; s < 16 * ch + 16; s += 4) {
+    for (int s = CH * ch; s < CH * ch + CH; s += 4) {
       const f32x4 xv = *reinterpret_cast<const f32x4*>(xr + s);
       a = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[0], areg[s + 0], a, 0, 0, 0);
       a = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[1], areg[s + 1], a, 0, 0, 0);

@@ -164,25 +164,96 @@ struct TileIO16 {
   }
 };
 
+// Loader for many threads (the fused kernel's whole workgroup): thread slot = (row, 4
+// features), consecutive threads on consecutive rows, one float4 per slot held in registers
+// between fetch and store.  The transposed arrays take 16-bit writes; consecutive rows land on
+// consecutive halves, so a wave's writes touch distinct banks.
+template <int DP, int NT>
+struct TileIO16Rows {
+  using TL = Tile16<DP>;
+  static constexpr int kSlots = kTile * (DP / 4);
+  static constexpr int kPer = (kSlots + NT - 1) / NT;
+
+  __device__ __forceinline__ static void fetch(f32x4 (&pre)[kPer], const float* __restrict__ X,
+                                               int D, bool vec_ok, int64_t row0, int valid,
+                                               int tid) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int idx = tid + q * NT;
+      const int row = idx % kTile;
+      const int c4 = (idx / kTile) * 4;
+      f32x4 v = {0.f, 0.f, 0.f, 0.f};
+      if (idx < kSlots && row < valid) {
+        const float* src = X + (row0 + row) * (int64_t)D + c4;
+        if (vec_ok) {
+          if (c4 < D) v = *reinterpret_cast<const f32x4*>(src);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (c4 + e < D) v[e] = src[e];
+        }
+      }
+      pre[q] = v;
+    }
+  }
+
+  template <class T, bool SPLIT>
+  __device__ __forceinline__ static void store(const TL& t, const f32x4 (&pre)[kPer], int tid) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int idx = tid + q * NT;
+      if (idx >= kSlots) continue;
+      const int row = idx % kTile;
+      const int c4 = (idx / kTile) * 4;
+      const int p = tpos(row);
+#pragma unroll
+      for (int sq = 0; sq < 2; ++sq) {
+        const int f0 = c4 + sq * DP;
+        uint16_t hi[4], lo[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float v = sq ? pre[q][e] * pre[q][e] : pre[q][e];
+          T hh, ll;
+          split16<T>(v, hh, ll);
+          hi[e] = bits16<T>(hh);
+          lo[e] = SPLIT ? bits16<T>(ll) : (uint16_t)0;
+        }
+        const u32x2 vh = {(unsigned)hi[0] | ((unsigned)hi[1] << 16), (unsigned)hi[2] | ((unsigned)hi[3] << 16)};
+        *reinterpret_cast<u32x2*>(t.rm_hi + row * TL::RS + f0) = vh;
+        if (SPLIT) {
+          const u32x2 vl = {(unsigned)lo[0] | ((unsigned)lo[1] << 16), (unsigned)lo[2] | ((unsigned)lo[3] << 16)};
+          *reinterpret_cast<u32x2*>(t.rm_lo + row * TL::RS + f0) = vl;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          t.xt_hi[(f0 + e) * TL::TS + p] = hi[e];
+          if (SPLIT) t.xt_lo[(f0 + e) * TL::TS + p] = lo[e];
+        }
+      }
+    }
+  }
+};
+
 // E-step, 16-bit operands.  bh/bl: per k-step s (16 features), the lane's 8 constants
-// A[16s + 8h + e][comp] as hi/lo fragments.  Chains of two k-steps (32 features) are joined
-// with TwoSum exactly as in the FP32 form.
-template <int DP, class T, bool SPLIT>
+// A[16s + 8h + e][comp] as hi/lo fragments.  With COMP, chains of two k-steps (32 features)
+// are joined with TwoSum exactly as in the FP32 form; without, one chain (lo = 0).
+template <int DP, class T, bool SPLIT, bool COMP>
 __device__ __forceinline__ void estep16(const Tile16<DP>& t, int j, int h,
                                         const typename P16<T>::v8 (&bh)[2 * DP / 16],
                                         const typename P16<T>::v8 (&bl)[2 * DP / 16], float cval,
                                         f32x16& hi, f32x16& lo) {
   using V = typename P16<T>::v8;
   constexpr int NS = 2 * DP / 16;
+  constexpr int CH = COMP ? 2 : NS;  // k-steps per accumulation chain
   const uint16_t* ah = t.rm_hi + j * Tile16<DP>::RS + 8 * h;
   const uint16_t* al = t.rm_lo + j * Tile16<DP>::RS + 8 * h;
 #pragma unroll
-  for (int ch = 0; ch < NS / 2; ++ch) {
+  for (int ch = 0; ch < NS / CH; ++ch) {
     f32x16 a;
 #pragma unroll
     for (int r = 0; r < 16; ++r) a[r] = (ch == 0) ? cval : 0.f;
 #pragma unroll
-    for (int s = 2 * ch; s < 2 * ch + 2; ++s) {
+    for (int s = CH * ch; s < CH * ch + CH; ++s) {
       const V xh = __builtin_bit_cast(V, *reinterpret_cast<const u32x4*>(ah + 16 * s));
       a = P16<T>::mfma(xh, bh[s], a);
       if (SPLIT) {

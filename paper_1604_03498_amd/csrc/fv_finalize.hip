@@ -99,14 +99,18 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(
 __global__ __launch_bounds__(kThreads) void l2_kernel(float* __restrict__ out,
                                                       const double* __restrict__ normpart,
                                                       int nblk, int len) {
-  __shared__ double inv;
+  __shared__ double red[kThreads];
   const int b = blockIdx.y;
-  if (threadIdx.x == 0) {
-    double ss = 0.0;
-    for (int i = 0; i < nblk; ++i) ss += normpart[(size_t)b * nblk + i];
-    inv = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
-  }
+  // fixed-order sum of the frame's block sums: strided per thread, then a tree
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kThreads) ss += normpart[(size_t)b * nblk + i];
+  red[threadIdx.x] = ss;
   __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double inv = red[0] > 0.0 ? 1.0 / sqrt(red[0]) : 0.0;
   if (inv == 0.0) return;
   float* o = out + (size_t)b * len;
   const int base = blockIdx.x * kThreads * kL2PerThread + threadIdx.x;

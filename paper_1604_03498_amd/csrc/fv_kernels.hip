@@ -96,19 +96,10 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
       f32x16 hi, lo;
       estep_f32<DP>(xb + j * XS + DP * h, areg, cval, hi, lo);
 
-      // Per row: this wave's max and sum of exp2(logit - max) over its 32 components; lane
-      // j == 0 of each half publishes them for the cross-wave combine.
+      // Per row: this wave's max and sum of exp2(logit - max) over its 32 components,
+      // published for the cross-wave combine.
       f32x16 e;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float m = allreduce32(hi[r], MaxOp());
-        e[r] = fast_exp2((hi[r] - m) + lo[r]);
-        const float sum = allreduce32(e[r], AddOp());
-        if (j == 0) {
-          red_m[w][crow(r, h)] = m;
-          red_s[w][crow(r, h)] = sum;
-        }
-      }
+      softmax_wave(hi, lo, e, red_m[w], red_s[w], j, h);
       __syncthreads();
       if (tid < kTile) {  // one thread per row combines the W partial (max, sum) pairs
         const int row = tid;

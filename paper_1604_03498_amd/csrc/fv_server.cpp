@@ -262,9 +262,20 @@ void scheduler(fv_server* s) {
       }
     }
     if (s->stop && s->queue.empty() && !any_busy) break;
-    // 3. admission: FIFO into free lanes while frames, rows and budget allow
+    // 3. admission: FIFO into free lanes while frames, rows and budget allow.  With a batching
+    //    window, a launch that could not be filled yet waits for its oldest request to age.
     bool launched = false;
+    double window_left_us = 0;
+    if (s->cfg.batch_window_us > 0 && !s->queue.empty() && !s->stop) {
+      int64_t qrows = 0;
+      for (const Request* r : s->queue) qrows += r->rows;
+      const double age = t - s->queue.front()->t_submit;
+      if ((int)s->queue.size() < s->cfg.max_batch_frames && qrows < s->cfg.max_batch_rows &&
+          age < s->cfg.batch_window_us)
+        window_left_us = s->cfg.batch_window_us - age;
+    }
     for (Lane& L : s->lanes) {
+      if (window_left_us > 0) break;
       if (L.busy || s->queue.empty()) continue;
       std::vector<int64_t> sizes;
       int64_t rows = 0;
@@ -315,7 +326,10 @@ void scheduler(fv_server* s) {
     // 4. wait for work or for a running launch to finish
     bool busy_now = false;
     for (Lane& L : s->lanes) busy_now |= L.busy;
-    if (busy_now)
+    if (window_left_us > 0)
+      s->cv_work.wait_for(lk, std::chrono::duration<double, std::micro>(
+                                  busy_now ? std::min(window_left_us, 20.0) : window_left_us));
+    else if (busy_now)
       s->cv_work.wait_for(lk, std::chrono::microseconds(20));
     else if (s->queue.empty() && !s->stop)
       s->cv_work.wait(lk);

@@ -25,12 +25,6 @@ using namespace dev;
 
 constexpr int kSliceWaves = 4;
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <int DP>
 __global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,

@@ -34,7 +34,8 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("precision", ctypes.c_int),
                 ("flags", ctypes.c_uint), ("max_queue", ctypes.c_int), ("n_streams", ctypes.c_int),
                 ("max_batch_frames", ctypes.c_int), ("max_batch_rows", ctypes.c_int64),
-                ("deadline_ms", ctypes.c_double), ("executor", ctypes.c_int),
+                ("deadline_ms", ctypes.c_double), ("batch_window_us", ctypes.c_double),
+                ("executor", ctypes.c_int),
                 ("fake_K", ctypes.c_int), ("fake_D", ctypes.c_int),
                 ("fake_us_per_krow", ctypes.c_double), ("fake_fail_every", ctypes.c_int)]
 

@@ -69,18 +69,18 @@ def test_alone_equals_mix_bitwise(fv, K, D, prec):
     target = fvsynth.frame(g, 12500, 77, 0.05)
     others = [fvsynth.frame(g, n, 900 + i, 0.05) for i, n in enumerate([8000, 3000, 18000, 500, 9999])]
     h = fv.gmm_load(g.weights, g.means, g.variances)
-    blocker = fvsynth.frame(g, 60000, 5, 0.05)
     with fv.Server(h, fv.server_config(precision=prec, n_streams=1)) as s:
         t = s.submit(target)
         alone = drain(s, [t])[t]
-        # one stream: while the large first frame runs, the rest queue and share one launch
-        ts = [s.submit(blocker)] + [s.submit(o) for o in others[:3]] + [s.submit(target)] + \
-             [s.submit(o) for o in others[3:]]
+    assert alone[0] == fv.OK and alone[2]["batch_frames"] == 1
+    # a batching window long enough for all submissions puts the target in a shared launch
+    with fv.Server(h, fv.server_config(precision=prec, n_streams=1, batch_window_us=2e5)) as s:
+        ts = [s.submit(o) for o in others[:3]] + [s.submit(target)] + [s.submit(o) for o in others[3:]]
         res = drain(s, ts)
-    mixed = res[ts[4]]
-    assert alone[0] == fv.OK and mixed[0] == fv.OK
-    say(f"  alone launch frames={alone[2]['batch_frames']}, mixed launch frames={mixed[2]['batch_frames']}")
-    assert alone[2]["batch_frames"] == 1 and mixed[2]["batch_frames"] > 1
+    mixed = res[ts[3]]
+    assert mixed[0] == fv.OK
+    say(f"  alone: 1 frame per launch; mixed: {mixed[2]['batch_frames']} frames in the launch")
+    assert mixed[2]["batch_frames"] == 6
     assert np.array_equal(alone[1], mixed[1])
     e = errors(alone[1], oracle.encode_gmm(target, g))
     say(f"  vs oracle: {e}")

@@ -137,3 +137,11 @@ def test_destroy_with_work_outstanding():
     for _ in range(5):
         s.submit(np.zeros((500, D), np.float32))
     s.close()                                        # drops queued requests, waits for the launch
+
+
+def test_batching_window_collects_frames():
+    with fake(n_streams=1, batch_window_us=1e5, fake_us_per_krow=10.0) as s:
+        tickets = [s.submit(np.zeros((100, D), np.float32)) for _ in range(5)]
+        res = drain(s, tickets)
+        assert all(res[t][0] == fv.OK and res[t][2]["batch_frames"] == 5 for t in tickets)
+        assert res[tickets[0]][2]["t_admit_us"] - res[tickets[0]][2]["t_submit_us"] >= 0.9e5
