@@ -105,19 +105,26 @@ __device__ __forceinline__ float reduce_scatter16(const float (&v)[16], int j, O
 __device__ __forceinline__ constexpr int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
 // Soft assignment, wave-local part: for the tile's 32 rows and this wave's 32 components,
-// e = exp2((hi - m_w) + lo) with m_w the wave's row maximum; the row maxima and the row sums
-// of e are published to red_m[row], red_s[row] (this wave's slice of the exchange arrays).
+// e = exp2((hi - m_w) + lo) with m_w the wave's row maximum.  The row maxima and the row sums
+// of e are published for the cross-wave combine at xm[row * W + w], xs[row * W + w]; `loc`
+// (32 floats, private to this wave) carries the maxima back to every lane of the wave.
+template <int W>
 __device__ __forceinline__ void softmax_wave(const f32x16& hi, const f32x16& lo, f32x16& e,
-                                             float* red_m, float* red_s, int j, int h) {
+                                             float* xm, float* xs, float* loc, int w, int j,
+                                             int h) {
   float v[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = hi[r];
   const float mrow = reduce_scatter16(v, j, MaxOp());
-  if (!(j & 1)) red_m[crow(j >> 1, h)] = mrow;
+  const int myrow = crow(j >> 1, h);
+  if (!(j & 1)) {
+    loc[myrow] = mrow;
+    xm[myrow * W + w] = mrow;
+  }
   wave_sync();
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const f32x4 m = *reinterpret_cast<const f32x4*>(red_m + 8 * q + 4 * h);
+    const f32x4 m = *reinterpret_cast<const f32x4*>(loc + 8 * q + 4 * h);
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int r = 4 * q + p;
@@ -126,7 +133,35 @@ __device__ __forceinline__ void softmax_wave(const f32x16& hi, const f32x16& lo,
     }
   }
   const float srow = reduce_scatter16(v, j, AddOp());
-  if (!(j & 1)) red_s[crow(j >> 1, h)] = srow;
+  if (!(j & 1)) xs[myrow * W + w] = srow;
+}
+
+// Cross-wave combine, after a workgroup barrier: the lane pair that owns row crow(j>>1, h)
+// reads the W published (max, sum) pairs of its row and forms M = max_v m_v and
+// Z = sum_v s_v 2^(m_v - M).  Returns the scale of this wave's e for that row,
+// 2^(m_w - M) / Z (0 for rows past `valid`), and M and log2 Z through the references.
+template <int W>
+__device__ __forceinline__ float softmax_combine(const float* xm, const float* xs, int w, int j,
+                                                 int h, int valid, float& M, float& L2Z) {
+  const int row = crow(j >> 1, h);
+  float m[W], sv[W];
+#pragma unroll
+  for (int v = 0; v < W; ++v) {
+    m[v] = xm[row * W + v];
+    sv[v] = xs[row * W + v];
+  }
+  M = m[0];
+#pragma unroll
+  for (int v = 1; v < W; ++v) M = fmaxf(M, m[v]);
+  float Z = 0.f, mine = 0.f;
+#pragma unroll
+  for (int v = 0; v < W; ++v) {
+    const float sc = fast_exp2(m[v] - M);
+    Z += sv[v] * sc;
+    if (v == w) mine = sc;
+  }
+  L2Z = log2f(Z);
+  return row < valid ? mine / Z : 0.f;
 }
 
 // ---- descriptor tile staging ------------------------------------------------------------

@@ -39,9 +39,9 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
   constexpr int XS = IO::XS;
 
   __shared__ __attribute__((aligned(16))) float xs[2][kTile * XS];
-  __shared__ __attribute__((aligned(16))) float red_m[W][kTile];
-  __shared__ __attribute__((aligned(16))) float red_s[W][kTile];
-  __shared__ __attribute__((aligned(16))) float fac[W][kTile];
+  __shared__ __attribute__((aligned(16))) float xm[kTile * W];   // [row][wave] maxima
+  __shared__ __attribute__((aligned(16))) float xsum[kTile * W]; // [row][wave] sums
+  __shared__ __attribute__((aligned(16))) float loc[W][kTile];   // wave-private scratch
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -99,38 +99,27 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
       // Per row: this wave's max and sum of exp2(logit - max) over its 32 components,
       // published for the cross-wave combine.
       f32x16 e;
-      softmax_wave(hi, lo, e, red_m[w], red_s[w], j, h);
+      softmax_wave<W>(hi, lo, e, xm, xsum, loc[w], w, j, h);
       __syncthreads();
-      if (tid < kTile) {  // one thread per row combines the W partial (max, sum) pairs
-        const int row = tid;
-        float M = red_m[0][row];
-#pragma unroll
-        for (int v = 1; v < W; ++v) M = fmaxf(M, red_m[v][row]);
-        float sc[W];
-        float Z = 0.f;
-#pragma unroll
-        for (int v = 0; v < W; ++v) {
-          sc[v] = fast_exp2(red_m[v][row] - M);
-          Z += red_s[v][row] * sc[v];
-        }
+      {
+        float M, L2Z;
+        const float f = softmax_combine<W>(xm, xsum, w, j, h, valid, M, L2Z);
         if (LSE) {
-          if (row < valid)
-            lse[(size_t)group * lse_stride + row0 + (int64_t)t * kTile + row] =
-                make_float2(M, log2f(Z));
+          const int row = crow(j >> 1, h);
+          if (w == 0 && !(j & 1) && row < valid)
+            lse[(size_t)group * lse_stride + row0 + (int64_t)t * kTile + row] = make_float2(M, L2Z);
         } else {
-          const float inv = (row < valid) ? 1.0f / Z : 0.0f;
+          if (!(j & 1)) loc[w][crow(j >> 1, h)] = f;
+          wave_sync();
 #pragma unroll
-          for (int v = 0; v < W; ++v) fac[v][row] = sc[v] * inv;
+          for (int q = 0; q < 4; ++q) {
+            const f32x4 fq = *reinterpret_cast<const f32x4*>(&loc[w][8 * q + 4 * h]);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) e[4 * q + p] *= fq[p];  // gamma, in place
+          }
         }
       }
       if (!LSE) {
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const f32x4 f = *reinterpret_cast<const f32x4*>(&fac[w][8 * q + 4 * h]);
-#pragma unroll
-          for (int p = 0; p < 4; ++p) e[4 * q + p] *= f[p];  // gamma, in place
-        }
 #pragma unroll
         for (int r = 0; r < 16; ++r) s0 += e[r];
         stats_f32<DP>(xb, h, j, e, acc);
