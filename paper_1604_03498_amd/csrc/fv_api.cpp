@@ -410,7 +410,7 @@ size_t batch_device_bytes(const fv_gmm* g, const int64_t* sizes, int B) {
     groups += (ni + kGroupItems - 1) / kGroupItems;
   }
   const size_t out_len = (size_t)2 * c.K * c.D;
-  size_t n = align256((size_t)items * slot_floats(c) * 4) + align256((size_t)groups * slot_floats(c) * 8) +
+  size_t n = align256((size_t)items * slot_floats(c) * 4) +
              align256((size_t)B * finalize_blocks(c) * 8) +
              (split ? align256((size_t)lse_groups(c) * rows * 8) : 0) +
              align256((size_t)B * sizeof(Frame)) + align256((size_t)items * sizeof(Item)) +
@@ -687,20 +687,18 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   const int nblk = fv::finalize_blocks(c);
   const size_t out_len = (size_t)2 * c.K * c.D;
   const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
-  const size_t b_grp = align256((size_t)n_groups * fv::slot_floats(c) * 8);
   const size_t b_norm = align256((size_t)nblk * 8);
   const size_t b_lse = (path == Path::kSplit) ? align256((size_t)G * N * 8) : 0;
   const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)N * c.D * 4);
   const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256(out_len * 4);
-  int rc = ensure_dev(ws, b_part + b_grp + b_norm + b_lse + b_x + b_out, s);
+  int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_x + b_out, s);
   if (rc) return rc;
   char* base = ws->dev;
   float* partials = reinterpret_cast<float*>(base);
-  double* gbuf = reinterpret_cast<double*>(base + b_part);
-  double* normpart = reinterpret_cast<double*>(base + b_part + b_grp);
-  float2* lse = reinterpret_cast<float2*>(base + b_part + b_grp + b_norm);
-  float* xdev = reinterpret_cast<float*>(base + b_part + b_grp + b_norm + b_lse);
-  float* odev = reinterpret_cast<float*>(base + b_part + b_grp + b_norm + b_lse + b_x);
+  double* normpart = reinterpret_cast<double*>(base + b_part);
+  float2* lse = reinterpret_cast<float2*>(base + b_part + b_norm);
+  float* xdev = reinterpret_cast<float*>(base + b_part + b_norm + b_lse);
+  float* odev = reinterpret_cast<float*>(base + b_part + b_norm + b_lse + b_x);
 
   const float* Xd = X;
   if (!(flags & FV_X_DEVICE) && N > 0) {
@@ -726,8 +724,7 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
     }
     fv::Frame single{N, 0, n_items, 0, n_groups};
     hipEvent_t t1 = timing_begin(s);
-    FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, nullptr, n_groups, flags, Od, gbuf,
-                               normpart, s));
+    FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, nullptr, flags, Od, normpart, s));
     timing_end(t1, 1, s);
     return FV_OK;
   };
@@ -796,7 +793,6 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   const int nblk = fv::finalize_blocks(c);
   const size_t out_len = (size_t)2 * c.K * c.D;
   const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
-  const size_t b_grp = align256((size_t)n_groups * fv::slot_floats(c) * 8);
   const size_t b_norm = align256((size_t)B * nblk * 8);
   const size_t b_lse = (path == Path::kSplit) ? align256((size_t)G * rows * 8) : 0;
   const size_t b_frames = align256((size_t)B * sizeof(fv::Frame));
@@ -805,16 +801,15 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   const size_t b_tab = b_frames + b_items + b_groups;
   const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)rows * c.D * 4);
   const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256((size_t)B * out_len * 4);
-  int rc = ensure_dev(ws, b_part + b_grp + b_norm + b_lse + b_tab + b_x + b_out, s);
+  int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_tab + b_x + b_out, s);
   if (rc) return rc;
   rc = ensure_pinned(ws, b_tab);
   if (rc) return rc;
   char* base = ws->dev;
   float* partials = reinterpret_cast<float*>(base);
-  double* gbuf = reinterpret_cast<double*>(base + b_part);
-  double* normpart = reinterpret_cast<double*>(base + b_part + b_grp);
-  float2* lse = reinterpret_cast<float2*>(base + b_part + b_grp + b_norm);
-  char* tab = base + b_part + b_grp + b_norm + b_lse;
+  double* normpart = reinterpret_cast<double*>(base + b_part);
+  float2* lse = reinterpret_cast<float2*>(base + b_part + b_norm);
+  char* tab = base + b_part + b_norm + b_lse;
   fv::Frame* dframes = reinterpret_cast<fv::Frame*>(tab);
   fv::Item* ditems = reinterpret_cast<fv::Item*>(tab + b_frames);
   fv::Group* dgroups = reinterpret_cast<fv::Group*>(tab + b_frames + b_items);
@@ -869,8 +864,8 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
       timing_end(t0, 0, s);
     }
     hipEvent_t t1 = timing_begin(s);
-    FV_HIP(fv::launch_finalize(c, partials, dframes, fv::Frame{0, 0, 0, 0, 0}, B, dgroups, n_groups,
-                               flags, Od, gbuf, normpart, s));
+    FV_HIP(fv::launch_finalize(c, partials, dframes, fv::Frame{0, 0, 0, 0, 0}, B, dgroups, flags, Od,
+                               normpart, s));
     timing_end(t1, 1, s);
     return FV_OK;
   };

@@ -166,14 +166,15 @@ __device__ __forceinline__ float softmax_combine(const float* xm, const float* x
 
 // ---- descriptor tile staging ------------------------------------------------------------
 // Tile = 32 rows x DP features, fetched as float4 slots into registers by NT threads (thread
-// index `tid`), then written to LDS as [x (DP) | x^2 (DP) | pad 4] per row.  Rows past
-// `valid` and features past D are zero.
-template <int DP, int NT>
+// index `tid`), then written to LDS as [x (DP) | x^2 (DP) | pad 4] per row, or as [x (DP) |
+// pad 4] when SQ is false (the consumer squares on the fly; x * x is rounded the same way).
+// Rows past `valid` and features past D are zero.
+template <int DP, int NT, bool SQ = true>
 struct TileIO {
   static constexpr int kSlotsPerRow = DP / 4;
   static constexpr int kSlots = kTile * kSlotsPerRow;
   static constexpr int kPer = (kSlots + NT - 1) / NT;
-  static constexpr int XS = 2 * DP + 4;
+  static constexpr int XS = SQ ? 2 * DP + 4 : DP + 4;
 
   __device__ __forceinline__ static void fetch(f32x4 (&pre)[kPer], const float* __restrict__ X,
                                                int D, bool vec_ok, int64_t row0, int valid,
@@ -209,7 +210,7 @@ struct TileIO {
         const int c4 = (idx % kSlotsPerRow) * 4;
         const f32x4 v = pre[q];
         *reinterpret_cast<f32x4*>(xs + row * XS + c4) = v;
-        *reinterpret_cast<f32x4*>(xs + row * XS + DP + c4) = v * v;
+        if (SQ) *reinterpret_cast<f32x4*>(xs + row * XS + DP + c4) = v * v;
       }
     }
   }
@@ -256,6 +257,70 @@ __device__ __forceinline__ void estep_f32(const float* __restrict__ xr, const fl
   }
 }
 
+// Same E-step with the operand slice in LDS instead of registers: ar points at this lane's
+// row of the wave's slice, laid out [component j][2*DP (+ pad)] and offset by DP*h, and xr at
+// row j of an x-only tile; lanes of the upper half (h = 1) square x on the fly.  Operands and
+// accumulation order are those of estep_f32, so the logits are bitwise the same.
+template <int DP>
+__device__ __forceinline__ void estep_f32_lds(const float* __restrict__ xr,
+                                              const float* __restrict__ ar, int h, float cval,
+                                              f32x16& hi, f32x16& lo) {
+  constexpr int CH = 16;
+  // Operands of the next 4 steps are read while the current 4 MFMAs issue; the scheduling
+  // fences keep the compiler from hoisting all 2*DP operand reads (which would spill).
+  f32x4 xn = *reinterpret_cast<const f32x4*>(xr);
+  f32x4 an = *reinterpret_cast<const f32x4*>(ar);
+#pragma unroll
+  for (int ch = 0; ch < DP / CH; ++ch) {
+    f32x16 a;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = (ch == 0) ? cval : 0.f;
+#pragma unroll
+    for (int s = CH * ch; s < CH * ch + CH; s += 4) {
+      f32x4 xv = xn;
+      const f32x4 av = an;
+      if (s + 4 < DP) {
+        xn = *reinterpret_cast<const f32x4*>(xr + s + 4);
+        an = *reinterpret_cast<const f32x4*>(ar + s + 4);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xv[e] = h ? xv[e] * xv[e] : xv[e];
+      a = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[0], av[0], a, 0, 0, 0);
+      a = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[1], av[1], a, 0, 0, 0);
+      a = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[2], av[2], a, 0, 0, 0);
+      a = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[3], av[3], a, 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (ch == 0) {
+      hi = a;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lo[r] = 0.f;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float t = hi[r] + a[r];
+        const float bp = t - hi[r];
+        const float err = (hi[r] - (t - bp)) + (a[r] - bp);
+        hi[r] = t;
+        lo[r] += err;
+      }
+    }
+  }
+}
+
+// Copy of one wave's operand slice A[0..2DP)[comp0 .. comp0+32) into LDS as [j][k] with row
+// stride AS (coalesced 128-byte global reads of A's rows).
+template <int DP>
+__device__ __forceinline__ void load_a_lds(float* __restrict__ as, const float* __restrict__ A32,
+                                           int Kp, int comp0, int lane, int AS) {
+#pragma unroll 8
+  for (int i = 0; i < DP; ++i) {
+    const int k = 2 * i + (lane >> 5);
+    const int jj = lane & 31;
+    as[jj * AS + k] = A32[(size_t)k * Kp + comp0 + jj];
+  }
+}
+
 // ---- statistics on FP32 MFMA -----------------------------------------------------------------
 // acc[b] (rows = features 32b..32b+31 of [x, x^2], cols = the wave's components) +=
 // sum over the tile's rows of Xa[row][f] * gamma[row][comp].  gam is in E-step C layout.
@@ -270,6 +335,50 @@ __device__ __forceinline__ void stats_f32(const float* __restrict__ xb, int h, i
 #pragma unroll
     for (int b = 0; b < NB; ++b)
       acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(xrow[32 * b], gam[s], acc[b], 0, 0, 0);
+  }
+}
+
+// Same contraction from an x-only tile (row stride DP + 4): feature f < DP is x[f], feature
+// f >= DP is x[f - DP]^2, squared on the fly.
+template <int DP>
+__device__ __forceinline__ void stats_f32_x(const float* __restrict__ xb, int h, int j,
+                                            const f32x16& gam, f32x16 (&acc)[2 * DP / 32]) {
+  constexpr int XS = DP + 4;
+  constexpr int NB = 2 * DP / 32;
+  auto fetch = [&](int s, float (&v)[NB]) {
+    const float* xrow = xb + crow(s, h) * XS;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int f = 32 * b + j;
+      if (32 * (b + 1) <= DP)
+        v[b] = xrow[f];
+      else if (32 * b >= DP)
+        v[b] = xrow[f - DP];
+      else
+        v[b] = xrow[f < DP ? f : f - DP];
+    }
+  };
+  float vn[NB];
+  fetch(0, vn);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    float v[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) v[b] = vn[b];
+    if (s + 1 < 16) fetch(s + 1, vn);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int f = 32 * b + j;
+      float u = v[b];
+      if (32 * (b + 1) <= DP) {
+      } else if (32 * b >= DP) {
+        u = u * u;
+      } else {
+        u = f < DP ? u : u * u;
+      }
+      acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(u, gam[s], acc[b], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 

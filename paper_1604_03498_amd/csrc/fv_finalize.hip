@@ -3,13 +3,13 @@
 // followed by the improved-FV assembly and normalisation (Fisher-information scaling,
 // signed square root, L2).
 //
-//   group_reduce   gbuf[g][e] = sum over the group's slots (index order, double) of
-//                  partials[slot][e], for every element e of the [2DP+1][Kp] slot layout
-//   assemble       per frame and (k, d): S0, S1, S2 = sum of the frame's group rows (in
-//                  order); C1 = S1 - mu S0; C2 = S2 - 2 mu S1 + mu^2 S0;
-//                  u = C1 / sigma / (N sqrt w); v = (C2 / sigma^2 - S0) / (N sqrt(2 w));
-//                  optional signed square root; block sums of squares for the norm
-//   l2             phi /= ||phi||_2 (skipped when the norm is 0)
+//   reduce_assemble  one workgroup per (64-component block, dimension d) of a frame; its three
+//                    waves sum the S1[d], S2[d] and S0 rows of the frame's slots in double:
+//                    within a chunk group (at most 16 consecutive slots) in index order, then
+//                    the group sums in order.  Then C1 = S1 - mu S0; C2 = S2 - 2 mu S1 +
+//                    mu^2 S0; u = C1 / sigma / (N sqrt w); v = (C2 / sigma^2 - S0) /
+//                    (N sqrt(2 w)); optional signed square root; the block's sum of squares
+//   l2               phi /= ||phi||_2 (skipped when the norm is 0)
 // Every sum has a fixed order that depends only on the frame's own chunking, so a frame's
 // result is bitwise independent of the other frames in a batch.
 #include <math.h>
@@ -23,51 +23,84 @@ constexpr unsigned kFlagNoPower = 4u;
 constexpr unsigned kFlagNoL2 = 8u;
 constexpr int kThreads = 256;
 constexpr int kL2PerThread = 4;
+constexpr int kCompBlock = 64;   // components per reduce_assemble workgroup (one per lane)
+constexpr int kRedThreads = 192; // three waves: S1 row, S2 row, S0 row
 
-__global__ __launch_bounds__(kThreads) void group_reduce_kernel(
-    const float* __restrict__ partials, const Group* __restrict__ groups, int n_items_single,
-    int slot, double* __restrict__ gbuf) {
-  const int g = blockIdx.y;
-  int item0, nitems;
-  if (groups != nullptr) {
-    const Group gr = groups[g];
-    item0 = gr.item0;
-    nitems = gr.nitems;
-  } else {
-    item0 = g * kGroupItems;
-    nitems = n_items_single - item0 < kGroupItems ? n_items_single - item0 : kGroupItems;
-  }
-  const int e = blockIdx.x * kThreads + threadIdx.x;
-  if (e >= slot) return;
-  const float* p = partials + (size_t)item0 * slot + e;
-  double acc = 0.0;
-  for (int i = 0; i < nitems; ++i) acc += (double)p[(size_t)i * slot];
-  gbuf[(size_t)g * slot + e] = acc;
+// Loads of one group's slots for one (row, component), unconditional so that all of them are
+// in flight together: slot indices are clamped to [0, nclamp) (nclamp >= 1 valid slots from p)
+// and values past n (or for a padded component) are replaced by +0.0, which leaves the
+// index-order double sum unchanged (the sum never holds -0.0).
+__device__ inline void load_group(const float* __restrict__ p, int nclamp, int n, size_t slot,
+                                  bool ok, float (&v)[kGroupItems]) {
+#pragma unroll
+  for (int i = 0; i < kGroupItems; ++i) v[i] = p[(size_t)min(i, nclamp - 1) * slot];
+#pragma unroll
+  for (int i = 0; i < kGroupItems; ++i) v[i] = (ok && i < n) ? v[i] : 0.f;
 }
 
-__global__ __launch_bounds__(kThreads) void assemble_kernel(
-    const double* __restrict__ gbuf, const Frame* __restrict__ frames, Frame single, int K, int D,
-    int DP, int Kp, const double* __restrict__ mu64, const double* __restrict__ isd64,
+__device__ inline double sum_group(const float (&v)[kGroupItems]) {
+  double a = 0.0;
+#pragma unroll
+  for (int i = 0; i < kGroupItems; ++i) a += (double)v[i];
+  return a;
+}
+
+__global__ __launch_bounds__(kRedThreads) void reduce_assemble_kernel(
+    const float* __restrict__ partials, const Frame* __restrict__ frames, Frame single,
+    const Group* __restrict__ groups, int K, int D, int DP, int Kp, int nkb,
+    const double* __restrict__ mu64, const double* __restrict__ isd64,
     const double* __restrict__ ivar64, const double* __restrict__ cu64,
     const double* __restrict__ cv64, unsigned flags, float* __restrict__ out,
     double* __restrict__ normpart) {
-  __shared__ double red[kThreads];
+  __shared__ double sv[3][kCompBlock];
   const int b = blockIdx.y;
   const Frame fr = frames != nullptr ? frames[b] : single;
-  const int KD = K * D;
-  const int idx = blockIdx.x * kThreads + threadIdx.x;
+  const int kb = blockIdx.x % nkb;
+  const int d = blockIdx.x / nkb;
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int k = kb * kCompBlock + lane;
+  const bool kok = k < K;
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
-  double ss = 0.0;
-  if (idx < KD) {
-    const int k = idx % K;  // consecutive threads read consecutive components
-    const int d = idx / K;
-    double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-    const double* p = gbuf + (size_t)fr.group0 * slot;
-    for (int g = 0; g < fr.ngroups; ++g, p += slot) {
-      S0 += p[(size_t)(2 * DP) * Kp + k];
-      S1 += p[(size_t)d * Kp + k];
-      S2 += p[(size_t)(DP + d) * Kp + k];
+  const int row = wv == 0 ? d : (wv == 1 ? DP + d : 2 * DP);
+  const float* base = partials + (size_t)row * Kp + (kok ? k : 0);
+
+  double tot = 0.0;
+  for (int g = 0; g < fr.ngroups; g += 2) {
+    int i0a, na, i0b = 0, nb = 0;
+    if (groups != nullptr) {
+      const Group ga = groups[fr.group0 + g];
+      i0a = ga.item0;
+      na = ga.nitems;
+      if (g + 1 < fr.ngroups) {
+        const Group gb = groups[fr.group0 + g + 1];
+        i0b = gb.item0;
+        nb = gb.nitems;
+      }
+    } else {
+      i0a = fr.item0 + g * kGroupItems;
+      na = min(kGroupItems, fr.item0 + fr.nitems - i0a);
+      if (g + 1 < fr.ngroups) {
+        i0b = i0a + kGroupItems;
+        nb = min(kGroupItems, fr.item0 + fr.nitems - i0b);
+      }
     }
+    float va[kGroupItems], vb[kGroupItems];
+    load_group(base + (size_t)i0a * slot, na, na, slot, kok, va);
+    if (nb > 0)
+      load_group(base + (size_t)i0b * slot, nb, nb, slot, kok, vb);
+    else
+      load_group(base + (size_t)i0a * slot, na, 0, slot, kok, vb);
+    tot += sum_group(va);
+    if (g + 1 < fr.ngroups) tot += sum_group(vb);
+  }
+  sv[wv][lane] = tot;
+  __syncthreads();
+  if (wv != 0) return;
+
+  double ss = 0.0;
+  if (kok) {
+    const double S0 = sv[2][lane], S1 = sv[0][lane], S2 = sv[1][lane];
     double u = 0.0, v = 0.0;
     if (fr.nrows > 0) {
       const int kd = k * D + d;
@@ -82,18 +115,16 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(
         v = (v > 0.0) ? sqrt(v) : ((v < 0.0) ? -sqrt(-v) : 0.0);
       }
     }
+    const int KD = K * D;
     float* o = out + (size_t)b * 2 * KD;
     o[k * D + d] = (float)u;
     o[KD + k * D + d] = (float)v;
     ss = u * u + v * v;
   }
-  red[threadIdx.x] = ss;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) normpart[(size_t)b * gridDim.x + blockIdx.x] = red[0];
+  // fixed-order butterfly over the wave
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) ss += __shfl_xor(ss, m);
+  if (lane == 0) normpart[(size_t)b * gridDim.x + blockIdx.x] = ss;
 }
 
 __global__ __launch_bounds__(kThreads) void l2_kernel(float* __restrict__ out,
@@ -123,23 +154,17 @@ __global__ __launch_bounds__(kThreads) void l2_kernel(float* __restrict__ out,
 
 }  // namespace
 
-int finalize_blocks(const Consts& c) { return (c.K * c.D + kThreads - 1) / kThreads; }
+int finalize_blocks(const Consts& c) { return ((c.K + kCompBlock - 1) / kCompBlock) * c.D; }
 
 hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* frames,
-                           Frame single, int B, const Group* groups, int n_groups, unsigned flags,
-                           float* out, double* gbuf, double* normpart, hipStream_t stream) {
+                           Frame single, int B, const Group* groups, unsigned flags, float* out,
+                           double* normpart, hipStream_t stream) {
   if (B <= 0) return hipSuccess;
-  const int slot = (int)slot_floats(c);
-  if (n_groups > 0) {
-    hipLaunchKernelGGL(group_reduce_kernel, dim3((slot + kThreads - 1) / kThreads, n_groups),
-                       dim3(kThreads), 0, stream, partials, groups, single.nitems, slot, gbuf);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   const int nblk = finalize_blocks(c);
-  hipLaunchKernelGGL(assemble_kernel, dim3(nblk, B), dim3(kThreads), 0, stream, gbuf, frames,
-                     single, c.K, c.D, c.DP, c.Kp, c.mu64, c.isd64, c.ivar64, c.cu64, c.cv64,
-                     flags, out, normpart);
+  const int nkb = (c.K + kCompBlock - 1) / kCompBlock;
+  hipLaunchKernelGGL(reduce_assemble_kernel, dim3(nblk, B), dim3(kRedThreads), 0, stream, partials,
+                     frames, single, groups, c.K, c.D, c.DP, c.Kp, nkb, c.mu64, c.isd64, c.ivar64,
+                     c.cu64, c.cv64, flags, out, normpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!(flags & kFlagNoL2)) {

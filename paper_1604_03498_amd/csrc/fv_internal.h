@@ -95,14 +95,15 @@ hipError_t launch_sliced(const Consts& c, int precision, const float* X, bool ve
 // Rows one workgroup of the second pass consumes per round (4 waves x 32-row tiles).
 int sliced_rows_per_wave_round();
 
-// Finalize: (1) every chunk group's slots are summed in index order in double precision into
-// gbuf[group]; (2) per frame, the group sums are added in order, turned into u and v, signed-
-// square-rooted unless flagged off, and written to out[frame][2*K*D]; (3) L2 normalisation
-// unless flagged off.  `frames` / `groups` are device tables, or null for one frame (B == 1,
-// `single`, groups of kGroupItems consecutive slots).
+// Finalize: per frame, the slots of every chunk group are summed in index order in double
+// precision and the group sums are added in order; the totals are turned into u and v,
+// signed-square-rooted unless flagged off, and written to out[frame][2*K*D]; then L2
+// normalisation unless flagged off.  `frames` / `groups` are device tables, or null for one
+// frame (B == 1, `single`, groups of kGroupItems consecutive slots).  normpart holds
+// B * finalize_blocks(c) doubles.
 hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* frames,
-                           Frame single, int B, const Group* groups, int n_groups, unsigned flags,
-                           float* out, double* gbuf, double* normpart, hipStream_t stream);
+                           Frame single, int B, const Group* groups, unsigned flags, float* out,
+                           double* normpart, hipStream_t stream);
 
 // Blocks per frame of the assembly step (size of normpart per frame).
 int finalize_blocks(const Consts& c);

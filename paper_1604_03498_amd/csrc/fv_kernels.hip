@@ -35,10 +35,15 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
     float2* __restrict__ lse, int64_t lse_stride) {
   constexpr int NT = 64 * W;
   constexpr int NB = 2 * DP / 32;  // 32-feature output blocks of the statistics contraction
-  using IO = TileIO<DP, NT>;
+  // At 8 waves (two per SIMD, 256 registers each) the statistics kernel cannot also hold its
+  // operand slice in registers without spilling; it keeps the slice in LDS and stages x only.
+  constexpr bool ALDS = !LSE && W == 8 && DP == 64;
+  constexpr int AS = 2 * DP + 4;  // LDS row stride of the operand slice
+  using IO = TileIO<DP, NT, !ALDS>;
   constexpr int XS = IO::XS;
 
   __shared__ __attribute__((aligned(16))) float xs[2][kTile * XS];
+  __shared__ __attribute__((aligned(16))) float as[ALDS ? W * kCompsPerWave * AS : 4];
   __shared__ __attribute__((aligned(16))) float xm[kTile * W];   // [row][wave] maxima
   __shared__ __attribute__((aligned(16))) float xsum[kTile * W]; // [row][wave] sums
   __shared__ __attribute__((aligned(16))) float loc[W][kTile];   // wave-private scratch
@@ -51,9 +56,13 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
   const int group = blockIdx.y;  // component group (LSE mode); 0 for the fused statistics
   const int comp = group * (W * kCompsPerWave) + w * kCompsPerWave + j;
 
-  float areg[DP];
+  float areg[ALDS ? 1 : DP];
+  if constexpr (ALDS) {
+    load_a_lds<DP>(as + w * kCompsPerWave * AS, A32, Kp, comp - j, lane, AS);
+  } else {
 #pragma unroll
-  for (int s = 0; s < DP; ++s) areg[s] = A32[(size_t)(s + DP * h) * Kp + comp];
+    for (int s = 0; s < DP; ++s) areg[s] = A32[(size_t)(s + DP * h) * Kp + comp];
+  }
   const float cval = c32[comp];
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
 
@@ -94,7 +103,10 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
       const float* xb = xs[buf];
 
       f32x16 hi, lo;
-      estep_f32<DP>(xb + j * XS + DP * h, areg, cval, hi, lo);
+      if constexpr (ALDS)
+        estep_f32_lds<DP>(xb + j * XS, as + (w * kCompsPerWave + j) * AS + DP * h, h, cval, hi, lo);
+      else
+        estep_f32<DP>(xb + j * XS + DP * h, areg, cval, hi, lo);
 
       // Per row: this wave's max and sum of exp2(logit - max) over its 32 components,
       // published for the cross-wave combine.
@@ -122,7 +134,10 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
       if (!LSE) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) s0 += e[r];
-        stats_f32<DP>(xb, h, j, e, acc);
+        if constexpr (ALDS)
+          stats_f32_x<DP>(xb, h, j, e, acc);
+        else
+          stats_f32<DP>(xb, h, j, e, acc);
       }
 
       if (has_next) IO::store(xs[buf ^ 1], pre, tid);
@@ -131,15 +146,19 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
 
     if (!LSE) {
       // Raw moments of this item: rows f = 0..2DP-1 (x, x^2 features), then S0.  Buffer
-      // stores: per-item resource bounded to one slot, lane offset comp*4, uniform row offset.
+      // stores: per-item resource bounded to one slot, per-lane offset (component and half),
+      // wave-uniform row offset.
       __amdgpu_buffer_rsrc_t rs = make_rsrc(partials + (size_t)it * slot,
                                             (uint32_t)(slot * sizeof(float)));
+      // the lane's half selects rows 4h..4h+3 of each 8-row group: per-lane offset, so the
+      // scalar offset stays uniform across the wave
+      const int vrow = comp * 4 + 4 * h * Kp * 4;
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[b][r]), rs, comp * 4,
-                                                (32 * b + crow(r, h)) * Kp * 4, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[b][r]), rs, vrow,
+                                                (32 * b + crow(r, 0)) * Kp * 4, 0);
       auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(s0), __float_as_uint(s0), false,
                                                 false);
       const float s0_total = __uint_as_float(p[0]) + __uint_as_float(p[1]);
