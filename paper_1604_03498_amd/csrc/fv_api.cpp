@@ -556,6 +556,15 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
           ahl[o] = f16_bits((_Float16)(v - (float)fh));
         }
 
+  // FP32 operand in fragment order (see Consts::A32)
+  std::vector<float> Af(A.size(), 0.f);
+  for (int cb = 0; cb < Kp / fv::kCompsPerWave; ++cb)
+    for (int gq = 0; gq < DP / 4; ++gq)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 4; ++e)
+          Af[(((size_t)cb * (DP / 4) + gq) * 64 + l) * 4 + e] =
+              A[(size_t)(4 * gq + e + DP * (l >> 5)) * Kp + cb * fv::kCompsPerWave + (l & 31)];
+
   // ---- one device block: A32 | c32 | 4 x 16-bit operand fragments | doubles
   const size_t nA = A.size();
   size_t off = 0;
@@ -577,7 +586,7 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
   char* blk = nullptr;
   FV_HIP(hipMalloc(&blk, total));
   std::vector<char> host(total, 0);
-  std::memcpy(host.data() + oA, A.data(), nA * 4);
+  std::memcpy(host.data() + oA, Af.data(), nA * 4);
   std::memcpy(host.data() + oc, cc.data(), (size_t)Kp * 4);
   std::memcpy(host.data() + oBH, abh.data(), nfrag * 2);
   std::memcpy(host.data() + oBL, abl.data(), nfrag * 2);

@@ -164,6 +164,38 @@ __device__ __forceinline__ float softmax_combine(const float* xm, const float* x
   return row < valid ? mine / Z : 0.f;
 }
 
+// ---- two-pass normaliser -----------------------------------------------------------------
+// The first pass leaves (row max m_g, log2 of the row sum s_g) per group g of up to 256
+// components at lse[g * stride + row].  fetch_lse loads them (ok: row inside the tile);
+// merge_lse forms M = max_g m_g and log2 Z, Z = sum_g s_g 2^(m_g - M), in group order.
+constexpr int kMaxLseGroups = kMaxK / (kMaxWaves * kCompsPerWave);
+
+__device__ __forceinline__ void fetch_lse(float2 (&l)[kMaxLseGroups], const float2* __restrict__ lse,
+                                          int G, int64_t stride, int64_t row, bool ok) {
+#pragma unroll
+  for (int g = 0; g < kMaxLseGroups; ++g)
+    if (ok && g < G) l[g] = lse[(size_t)g * stride + row];
+}
+
+__device__ __forceinline__ void merge_lse(const float2 (&l)[kMaxLseGroups], int G, float& M,
+                                          float& L2Z) {
+  M = l[0].x;
+  if (G == 1) {
+    L2Z = l[0].y;
+    return;
+  }
+  float Z = exp2f(l[0].y);
+#pragma unroll
+  for (int g = 1; g < kMaxLseGroups; ++g) {
+    if (g < G) {
+      const float Mn = fmaxf(M, l[g].x);
+      Z = Z * fast_exp2(M - Mn) + exp2f(l[g].y) * fast_exp2(l[g].x - Mn);
+      M = Mn;
+    }
+  }
+  L2Z = log2f(Z);
+}
+
 // ---- descriptor tile staging ------------------------------------------------------------
 // Tile = 32 rows x DP features, fetched as float4 slots into registers by NT threads (thread
 // index `tid`), then written to LDS as [x (DP) | x^2 (DP) | pad 4] per row, or as [x (DP) |
@@ -308,17 +340,29 @@ __device__ __forceinline__ void estep_f32_lds(const float* __restrict__ xr,
   }
 }
 
-// Copy of one wave's operand slice A[0..2DP)[comp0 .. comp0+32) into LDS as [j][k] with row
-// stride AS (coalesced 128-byte global reads of A's rows).
+// This lane's E-step operand values for component block cb from the fragment-ordered A32:
+// areg[s] = A[s + DP*h][32cb + j], sixteen-byte loads, 1 KB contiguous per wave load.
+template <int DP>
+__device__ __forceinline__ void load_areg(float (&areg)[DP], const float* __restrict__ A32,
+                                          int cb, int lane) {
+  const f32x4* src = reinterpret_cast<const f32x4*>(A32) + (size_t)cb * (DP / 4) * 64 + lane;
+#pragma unroll
+  for (int g = 0; g < DP / 4; ++g) {
+    const f32x4 v = src[g * 64];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) areg[4 * g + e] = v[e];
+  }
+}
+
+// Copy of one wave's operand slice (component block cb) into LDS as [j][k] with row stride
+// AS: lane (h, j) writes A[DP*h .. DP*h + DP)[32cb + j] in sixteen-byte pieces.
 template <int DP>
 __device__ __forceinline__ void load_a_lds(float* __restrict__ as, const float* __restrict__ A32,
-                                           int Kp, int comp0, int lane, int AS) {
-#pragma unroll 8
-  for (int i = 0; i < DP; ++i) {
-    const int k = 2 * i + (lane >> 5);
-    const int jj = lane & 31;
-    as[jj * AS + k] = A32[(size_t)k * Kp + comp0 + jj];
-  }
+                                           int cb, int lane, int AS) {
+  const f32x4* src = reinterpret_cast<const f32x4*>(A32) + (size_t)cb * (DP / 4) * 64 + lane;
+  float* dst = as + (lane & 31) * AS + DP * (lane >> 5);
+#pragma unroll 4
+  for (int g = 0; g < DP / 4; ++g) *reinterpret_cast<f32x4*>(dst + 4 * g) = src[g * 64];
 }
 
 // ---- statistics on FP32 MFMA -----------------------------------------------------------------

@@ -22,8 +22,11 @@ struct Consts {
   int Kp, DP;  // padded: Kp = 32 * Wg * groups, DP = D rounded up to a multiple of 16
   int Wg;      // waves per component group (1, 2, 4 or 8); one group when Kp <= 256, else
                // groups of 256 components (Wg = 8)
-  // E-step operand, log2(e)-scaled, [2*DP][Kp] f32: rows 0..DP-1 multiply x, rows DP..2DP-1
-  // multiply x^2; padded rows and columns are zero.
+  // E-step operand A, log2(e)-scaled, [2*DP][Kp] f32 (rows 0..DP-1 multiply x, rows
+  // DP..2DP-1 multiply x^2; padded rows and columns zero), stored in MFMA fragment order: for
+  // component block cb (32 components), step group g (4 steps) and lane l = 32h + j, the four
+  // values A[4g + e + DP*h][32cb + j], e = 0..3, at ((cb * DP/4 + g) * 64 + l) * 4, so a wave
+  // reads 1 KB contiguous per 16-byte load.
   const float* A32;
   // hi/lo splits of A32 for the bf16 and fp16 forms, as MFMA operand fragments: fragment
   // (s, h, comp) holds A[16s + 8h + e][comp], e = 0..7, at ((s*2 + h) * Kp + comp) * 8

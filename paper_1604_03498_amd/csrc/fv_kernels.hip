@@ -57,12 +57,10 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
   const int comp = group * (W * kCompsPerWave) + w * kCompsPerWave + j;
 
   float areg[ALDS ? 1 : DP];
-  if constexpr (ALDS) {
-    load_a_lds<DP>(as + w * kCompsPerWave * AS, A32, Kp, comp - j, lane, AS);
-  } else {
-#pragma unroll
-    for (int s = 0; s < DP; ++s) areg[s] = A32[(size_t)(s + DP * h) * Kp + comp];
-  }
+  if constexpr (ALDS)
+    load_a_lds<DP>(as + w * kCompsPerWave * AS, A32, comp / kCompsPerWave, lane, AS);
+  else
+    load_areg<DP>(areg, A32, comp / kCompsPerWave, lane);
   const float cval = c32[comp];
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
 

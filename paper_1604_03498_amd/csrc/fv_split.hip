@@ -47,8 +47,7 @@ __global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
   const int comp = q * kCompsPerWave + j;
 
   float areg[DP];
-#pragma unroll
-  for (int s = 0; s < DP; ++s) areg[s] = A32[(size_t)(s + DP * h) * Kp + comp];
+  load_areg<DP>(areg, A32, q, lane);
   const float cval = c32[comp];
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
   float* xw = xs[w];
@@ -67,7 +66,6 @@ __global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
       nrows = (int)(rem < (int64_t)P ? rem : (int64_t)P);
     }
     const int ntiles = (nrows + kTile - 1) / kTile;
-
     f32x16 acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -80,7 +78,8 @@ __global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
       const int64_t trow = row0 + (int64_t)t * kTile;
       f32x4 pre[IO::kPer];
       IO::fetch(pre, X, D, vec_ok != 0, trow, valid, lane);
-      // per-row normaliser from the first pass, merged over component groups
+      // per-row normaliser from the first pass, merged over component groups (the same
+      // arithmetic as merge_lse, one group at a time to save registers)
       if (lane < kTile) {
         float M = 0.f, L2Z = INFINITY;  // rows past the tile end get gamma = 0
         if (lane < valid) {
