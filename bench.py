@@ -16,8 +16,12 @@ precompute) happens once before timing and is reported separately.  Prints one J
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,6 +38,108 @@ DTYPE = {"fp32": "f32", "bf16_split": "bf16x3", "fp16_split": "f16x3", "bf16": "
 METRIC = "descriptors/sec encoded (K=256,D=64), BF16-split vs FP32; p99 frame latency"
 
 
+SRC_DIR = os.path.join(HERE, "paper_1604_03498_amd", "csrc")
+TRAFFIC_JSON = os.path.join(HERE, "profiles", "hbm_traffic.json")
+# statistics kernels of each path at D = 64 (as named in rocprofv3 traces)
+STATS_KERNELS = {
+    ("fp32", "split"): ["fused_f32_kernel<64, 8, true>", "sliced_f32_kernel<64>"],
+    ("fp32", "fused"): ["fused_f32_kernel<64, 8, false>"],
+    ("bf16_split", "split"): ["fused16_kernel<64, 8, true>", "sliced16_kernel<64>"],
+    ("bf16_split", "fused"): ["fused16_kernel<64, 8, false>"],
+    ("fp16_split", "split"): ["fused16_kernel<64, 8, true>", "sliced16_kernel<64>"],
+    ("fp16_split", "fused"): ["fused16_kernel<64, 8, false>"],
+}
+
+
+def kernel_source_hash():
+    """SHA-256 over the library's kernel and host sources: HBM counters taken on other sources
+    do not describe the kernels that run now."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(SRC_DIR)):
+        if name.endswith((".hip", ".inc", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(SRC_DIR, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def short_kernel(name):
+    m = re.search(r"::(\w+_kernel(?:<[^>]*>)?)", name.replace("(anonymous namespace)", "anon"))
+    return m.group(1) if m else name.split("(")[0][-60:]
+
+
+def load_traffic(form, path, launches_per_step):
+    """HBM bytes per statistics step from the committed counter summary, or None when it is
+    absent, lacks these kernels, or was taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    names = STATS_KERNELS.get((form, path))
+    per = t.get("kernels", {})
+    if not names or not all(n in per for n in names):
+        return None
+    fetch = sum(per[n]["read_bytes"] for n in names)
+    write = sum(per[n]["write_bytes"] for n in names)
+    return {"bytes": (fetch + write) * launches_per_step, "read_bytes": fetch * launches_per_step,
+            "write_bytes": write * launches_per_step, "kernels": names,
+            "from": "profiles/hbm_traffic.json"}
+
+
+def pmc_summary(fetch_dir, write_dir, calib_mb):
+    """Per-kernel HBM bytes from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, both with --calib-copy-mb): the counters of the plain calib_mb MiB device copy
+    at the end of the run give the scale from counter units to bytes.  Writes
+    profiles/hbm_traffic.json (with the source hash) and prints a markdown table."""
+    def per_dispatch(d, counter):
+        rows = []
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as f:
+                rows += [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+        acc = {}
+        for r in rows:
+            k = (r["Dispatch_Id"], r["Kernel_Name"])
+            acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+        return acc
+    fetch = per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = per_dispatch(write_dir, "WRITE_SIZE")
+    expect = calib_mb * (1 << 20)
+
+    def calib(acc):
+        copies = [v for (d, n), v in acc.items() if "copyBuffer" in n or "copy" in n.lower()]
+        return expect / (max(copies) * 1024.0) if copies else None
+    fr, wr = calib(fetch), calib(write)
+    if fr is None or wr is None:
+        raise SystemExit("no calibration copy kernel found in the counter runs")
+
+    def mean_by_kernel(acc):
+        out = {}
+        for (d, n), v in acc.items():
+            out.setdefault(short_kernel(n), []).append(v)
+        return {k: (sum(v) / len(v), len(v)) for k, v in out.items()}
+    mf, mw = mean_by_kernel(fetch), mean_by_kernel(write)
+    kernels = {}
+    for k in sorted(set(mf) & set(mw)):
+        if not k.endswith(">") and "_kernel" not in k:
+            continue
+        kernels[k] = {"read_bytes": mf[k][0] * 1024.0 * fr, "write_bytes": mw[k][0] * 1024.0 * wr,
+                      "fetch_kib_raw": mf[k][0], "write_kib_raw": mw[k][0], "dispatches": mf[k][1]}
+    out = {"source_sha256": kernel_source_hash(), "calibration_copy_mib": calib_mb,
+           "read_scale": fr, "write_scale": wr, "kernels": kernels}
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(f"scales: read x{fr:.3f}, write x{wr:.3f} (counter KiB -> bytes x1024)")
+    print("| kernel | dispatches | FETCH_SIZE (KiB, raw) | reads (MiB) | WRITE_SIZE (KiB, raw) | writes (MiB) |")
+    print("|---|---|---|---|---|---|")
+    for k, v in kernels.items():
+        print(f"| `{k}` | {v['dispatches']} | {v['fetch_kib_raw']:.1f} | {v['read_bytes'] / 2**20:.2f} | "
+              f"{v['write_kib_raw']:.1f} | {v['write_bytes'] / 2**20:.2f} |")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -47,12 +153,19 @@ def parse():
     ap.add_argument("--latency-samples", type=int, default=300)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-frame", action="store_true",
+                    help="skip the single-frame forms (profiling the batch alone)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch with the default tuning instead of the measuring autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="measured seconds of each open-loop serving run (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (HBM-counter scale)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
+                         "script made with --calib-copy-mb into profiles/hbm_traffic.json; no GPU")
     return ap.parse_args()
 
 
@@ -105,13 +218,15 @@ def time_form(fv, torch, h, Xd, off, out, form, steps, warmup, stream, lat_sampl
     return elapsed, st_ms / max(st_n, 1), st_n, fi_ms / max(fi_n, 1), np.array(lat)
 
 
-def roofline(form, K, D, ndesc, stats_avg_ms, path):
+def roofline(form, K, D, ndesc, stats_avg_ms, path, launches_per_step=1):
     alg = 8.0 * K * D * ndesc                      # algorithmic flops of the two contractions
     execd = alg * PRODUCTS[form] * (1.5 if path == "split" else 1.0)
     achieved = alg / (stats_avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[form]
+    tr = load_traffic(form, path, launches_per_step) if D == 64 else None
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4), "traffic": tr["bytes"] if tr else None,
+            "traffic_detail": tr,
             "mfma_util": round(execd / (stats_avg_ms * 1e-3) / 1e12 / peak, 4),
             "kernel": ("fused statistics kernel" if path == "fused" else
                        "two-pass statistics: row log-sum-exp pass + component-sliced pass"),
@@ -219,6 +334,9 @@ def cpu_baseline(g, frames, seconds):
 
 def main():
     a = parse()
+    if a.pmc_summary:
+        pmc_summary(a.pmc_summary[0], a.pmc_summary[1], a.calib_copy_mb or 256)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "single-GPU build: run with --gpus 1 (multi-GPU sharding is "
                                    "described in DESIGN.md, not implemented)"}))
@@ -240,7 +358,7 @@ def main():
     path = path_of(K, N, n_cu, os.environ.get("FV_PATH"))
 
     results, outputs = {}, {}
-    for form in forms:
+    for form in ([] if a.no_frame else forms):
         out = torch.empty(2 * K * D, dtype=torch.float32, device=dev)
         log(f"[bench] frame form={form} path={path} warmup={a.warmup} steps={a.steps}")
         el, st_avg, st_n, fi_avg, lat = time_form(fv, torch, h, Xd, off, out, form, a.steps,
@@ -264,8 +382,13 @@ def main():
         from paper_1604_03498_amd import autotune
         for form in forms:
             outb = torch.empty(offb.size - 1, 2 * K * D, dtype=torch.float32, device=dev)
-            tuned = autotune.tune_batch(hb, Xbd, offb, PREC_CODE[form], stream=stream, reps=3,
-                                        use_cache=False)
+            if a.no_autotune:
+                fv.set_tuning(hb)
+                tuned = {"batch_path": 1 if path_of(K, int(offb[-1]), n_cu, None) == "fused" else 2,
+                         "batch_chunk": fv.get_tuning(hb)["batch_chunk"] or 1024, "trials": []}
+            else:
+                tuned = autotune.tune_batch(hb, Xbd, offb, PREC_CODE[form], stream=stream, reps=3,
+                                            use_cache=False)
             bpath = {1: "fused", 2: "split"}[tuned["batch_path"]]
             log(f"[bench] batch form={form} tuned path={bpath} chunk={tuned['batch_chunk']} "
                 f"steps={a.batch_steps}")
@@ -301,6 +424,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {a.calib_copy_mb} MiB done")
 
+    if a.no_frame:
+        print(json.dumps({"metric": METRIC, "value": None, "batch": batch}), flush=True)
+        return
     prim = forms[0]
     res = results[prim]
     result = {

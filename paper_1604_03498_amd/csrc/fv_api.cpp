@@ -323,6 +323,12 @@ int fused_single_chunk(int64_t N, int device, int Wg) {
   return (int)std::min<int64_t>(per * fv::kTile, (int64_t)1 << 20);
 }
 
+// Grid width of the second pass.  Workgroups go to the eight XCDs (each with its own L2) in
+// round-robin order of their linear index x + y * gridDim.x; with gridDim.x a multiple of 8
+// every component slice y of chunk x runs on the same XCD, so the chunk's rows are fetched
+// from HBM once and then hit that XCD's L2.  Workgroups past the last chunk exit at once.
+int xcd_grid(int n) { return (n + 7) / 8 * 8; }
+
 // Chunk length of the second pass for a single frame: one round of resident workgroups over all
 // (chunk, slice) pairs, in whole rounds of the workgroup's 32-row tiles.
 int split_single_chunk(int64_t N, int device, int slices, int round, int wgs_per_cu) {
@@ -727,7 +733,8 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
         const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
         const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
         FV_HIP(run_lse(c, precision, Xd, vec_ok, N, n_tiles, grid1, lse, N, s));
-        FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, lse, N, partials, s));
+        FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
+                          partials, s));
       }
       timing_end(t0, 0, s);
     }
@@ -867,7 +874,7 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
         const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
         FV_HIP(run_lse(c, precision, Xd, vec_ok, rows, n_tiles, grid1, lse, rows, s));
         const int slices = c.Kp / fv::kCompsPerWave;
-        const int grid2 = std::max(1, std::min(n_items, 2 * device_cu_count(gmm->device) / slices + 1));
+        const int grid2 = xcd_grid(std::max(1, std::min(n_items, 2 * device_cu_count(gmm->device) / slices + 1)));
         FV_HIP(run_sliced(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
       }
       timing_end(t0, 0, s);

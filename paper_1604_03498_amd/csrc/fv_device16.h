@@ -202,7 +202,7 @@ struct TileIO16Rows {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int idx = tid + q * NT;
-      if (idx >= kSlots) continue;
+      if (kSlots % NT != 0 && idx >= kSlots) continue;  // (tid < NT: never when NT divides)
       const int row = idx % kTile;
       const int c4 = (idx / kTile) * 4;
       const int p = tpos(row);
