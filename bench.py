@@ -161,6 +161,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="measured seconds of each open-loop serving run (0: skip)")
+    ap.add_argument("--sweep", default="1,4,16,64",
+                    help="serving saturation sweep: arrival-rate multipliers of the 30 Hz streams, "
+                         "2 s each ('' to skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (HBM-counter scale)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -233,7 +236,8 @@ def roofline(form, K, D, ndesc, stats_avg_ms, path, launches_per_step=1):
             "kernel_avg_us": round(stats_avg_ms * 1e3, 3)}
 
 
-def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_streams=2):
+def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_streams=2,
+                rate_mult=1.0):
     """Open-loop serving run: 16 camera streams, Poisson arrivals at 30 Hz each, frames of
     8,000-32,000 descriptors (320x240 .. 640x480), D = 80, K = 512.  Latency is measured from
     each frame's scheduled arrival time to the completion of its encode (so a late submit
@@ -241,7 +245,8 @@ def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_
     import threading
     import fvsynth
     g = fvsynth.gmm(512, 80, 0)
-    events, sizes = fvsynth.serving_plan(duration_s=warm_s + seconds, pool=pool)
+    events, sizes = fvsynth.serving_plan(rate_hz=30.0 * rate_mult, duration_s=warm_s + seconds,
+                                         pool=pool)
     frames = {(st, p): fvsynth.frame(g, sizes[st], 100000 + 100 * st + p, 0.05)
               for st in range(len(sizes)) for p in range(pool)}
     h = fv.gmm_load(g.weights, g.means, g.variances, device=0)
@@ -256,11 +261,12 @@ def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_
     srv.stats(reset=True)
     sub = {}
     done = {}
-    n_events = len(events)
+    submitting = threading.Event()
+    submitting.set()
     finished = threading.Event()
 
     def collect():
-        while len(done) < n_events:
+        while submitting.is_set() or len(done) < len(sub):
             t = srv.next_done(100.0)
             if t is None:
                 continue
@@ -271,44 +277,58 @@ def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_
     th = threading.Thread(target=collect, daemon=True)
     th.start()
     t0 = time.perf_counter()
+    window = warm_s + seconds
+    dropped = 0
     for (t_arr, st, p) in events:
         wait = t0 + t_arr - time.perf_counter()
         if wait > 0:
             time.sleep(wait)
         ts = time.perf_counter()
+        if ts - t0 > window:         # saturated: arrivals past the window are not submitted
+            dropped += 1
+            continue
         while True:
             rc, tk = srv.try_submit(frames[(st, p)])
             if rc == fv.OK:
                 break
             time.sleep(0.0005)
         sub[tk] = (t_arr, ts - t0, sizes[st])
+    submitting.clear()
     finished.wait(timeout=120.0)
     wall = time.perf_counter() - t0
     stats = srv.stats()
     srv.close()
-    lat, rows, fails, frames_in_launch = [], 0, 0, []
+    # a frame counts if it completed after the warm-up; its completion time on the submitter's
+    # clock is its submit time plus the server's submit-to-done interval
+    lat, rows, fails, frames_in_launch, t_last = [], 0, 0, [], warm_s
     for tk, (t_arr, t_sub, n) in sub.items():
-        if tk not in done or t_arr < warm_s:
+        if tk not in done:
             continue
         rc, stt = done[tk]
+        t_end = t_sub + (stt["t_done_us"] - stt["t_submit_us"]) * 1e-6
+        if t_end < warm_s:
+            continue
         if rc != fv.OK:
             fails += 1
             continue
-        lat.append((stt["t_done_us"] - stt["t_submit_us"]) * 1e-3 + (t_sub - t_arr) * 1e3)
+        lat.append((t_end - t_arr) * 1e3)
         rows += n
+        t_last = max(t_last, t_end)
         frames_in_launch.append(stt["batch_frames"])
     lat = np.array(lat)
-    return {"form": form, "streams": len(sizes), "rate_hz_per_stream": 30.0,
+    return {"form": form, "streams": len(sizes), "rate_hz_per_stream": 30.0 * rate_mult,
             "frame_sizes": sorted(set(sizes)), "K": 512, "D": 80,
-            "measured_s": seconds, "frames": int(lat.size), "failed": fails,
-            "offered_desc_per_s": float(sum(sizes) * 30.0),
-            "throughput_desc_per_s": rows / seconds,
+            "measured_s": seconds, "frames": int(lat.size), "failed": fails, "not_submitted": dropped,
+            "offered_desc_per_s": float(sum(sizes) * 30.0 * rate_mult),
+            "throughput_desc_per_s": rows / max(t_last - warm_s, 1e-9),  # to the last completion
             "latency_ms_from_arrival": {"p50": float(np.percentile(lat, 50)) if lat.size else None,
                                         "p99": float(np.percentile(lat, 99)) if lat.size else None,
                                         "max": float(lat.max()) if lat.size else None},
             "mean_frames_per_launch": float(np.mean(frames_in_launch)) if frames_in_launch else None,
             "budget_bytes": int(budget_bytes), "peak_admitted_bytes": int(stats["peak_admitted_bytes"]),
             "gpu_busy_fraction": stats["busy_s"] / max(wall - warm_s, 1e-9), "n_streams": n_streams,
+            "busy_note": "sum of launch durations over the server's streams / wall time (can exceed 1 "
+                         "when launches on different streams overlap)",
             "input": "host memory (submit copies into pinned staging; H2D inside the launch)"}
 
 
@@ -414,6 +434,19 @@ def main():
             log(f"[bench]   p50 {r['latency_ms_from_arrival']['p50']:.3f} ms, p99 "
                 f"{r['latency_ms_from_arrival']['p99']:.3f} ms, {r['throughput_desc_per_s']:.3e} desc/s")
             serving.append(r)
+    sweep = []
+    if a.serving_seconds > 0 and a.sweep:
+        for mult in [float(x) for x in a.sweep.split(",") if x]:
+            log(f"[bench] serving sweep x{mult:g} (budget 2048 MiB, 2 s)")
+            r = run_serving(fv, 2.0, 0.5, 2 << 30, rate_mult=mult)
+            sweep.append({k: r[k] for k in ("rate_hz_per_stream", "offered_desc_per_s",
+                                             "throughput_desc_per_s", "latency_ms_from_arrival",
+                                             "mean_frames_per_launch", "gpu_busy_fraction",
+                                             "frames", "failed", "not_submitted")})
+            p99 = r["latency_ms_from_arrival"]["p99"]
+            log(f"[bench]   offered {r['offered_desc_per_s']:.3e}, served {r['throughput_desc_per_s']:.3e} "
+                f"desc/s, p99 {p99 if p99 is None else round(p99, 2)} ms, "
+                f"frames/launch {r['mean_frames_per_launch']}, not submitted {r['not_submitted']}")
 
     if a.calib_copy_mb > 0:
         n = a.calib_copy_mb * (1 << 20) // 4
@@ -444,6 +477,8 @@ def main():
         result["batch"] = batch
     if serving:
         result["serving"] = serving
+    if sweep:
+        result["serving_sweep"] = sweep
     if not a.no_cpu_baseline:
         import oracle
         from oracle.metrics import errors
