@@ -332,6 +332,51 @@ def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_
             "input": "host memory (submit copies into pinned staging; H2D inside the launch)"}
 
 
+def c5_capacity(fv, torch, dev, stream, forms, steps):
+    """GPU throughput at the serving shape with inputs already in device memory: one frame of
+    each of the 16 camera streams' sizes (8,000-32,000 descriptors, K = 512, D = 80) encoded
+    as one batch (graph replays).  Set beside the serving sweep, it separates the device's
+    capacity from the host-side staging of the serving runs."""
+    import fvsynth
+    g = fvsynth.gmm(512, 80, 0)
+    _, sizes = fvsynth.serving_plan(duration_s=1.0)
+    frames = [fvsynth.frame(g, n, 100000 + 100 * st, 0.05) for st, n in enumerate(sizes)]
+    X = np.concatenate(frames)
+    off = np.zeros(len(frames) + 1, np.int64)
+    off[1:] = np.cumsum([f.shape[0] for f in frames])
+    h = fv.gmm_load(g.weights, g.means, g.variances, device=0)
+    Xd = torch.from_numpy(X).to(dev)
+    out = {}
+    for form in forms:
+        o = torch.empty(len(frames), 2 * 512 * 80, dtype=torch.float32, device=dev)
+        el, st_avg, _, fi_avg, _ = time_form(fv, torch, h, Xd, off, o, form, steps, 2, stream, 0, True)
+        out[form] = {"value": int(off[-1]) * steps / el, "ms_per_batch": el * 1e3 / steps,
+                     "statistics_us": round(st_avg * 1e3, 2), "finalize_us": round(fi_avg * 1e3, 2)}
+        log(f"[bench] c5 capacity form={form}: {out[form]['value']:.3e} desc/s")
+    out["config"] = {"K": 512, "D": 80, "frames": len(frames), "descriptors": int(off[-1])}
+    return out
+
+
+def oracle_c1():
+    """The oracle on the small configuration (K = 64, D = 64, N = 2,000): seconds per frame on
+    one thread, and frames/s with whole frames spread over the host threads."""
+    import fvsynth
+    import oracle
+    g, X, _ = fvsynth.workload("c1_oracle_k64_d64_n2000")
+    t0 = time.perf_counter()
+    oracle.encode_batch(X, np.array([0, X.shape[0]], np.int64), g.weights, g.means, g.variances,
+                        nthreads=1)
+    one = time.perf_counter() - t0
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    Xs = np.concatenate([X] * nthreads)
+    o = np.arange(nthreads + 1, dtype=np.int64) * X.shape[0]
+    t0 = time.perf_counter()
+    oracle.encode_batch(Xs, o, g.weights, g.means, g.variances, nthreads=nthreads)
+    allc = time.perf_counter() - t0
+    return {"seconds_per_frame_1_thread": one, "frames_per_s_all_threads": nthreads / allc,
+            "threads": nthreads, "workload": "c1_oracle_k64_d64_n2000"}
+
+
 def cpu_baseline(g, frames, seconds):
     """The FP64 oracle on the host cores over a bounded sample of the same workload: whole
     copies of the workload frame are encoded, spread over threads, until `seconds` elapse."""
@@ -448,6 +493,10 @@ def main():
                 f"desc/s, p99 {p99 if p99 is None else round(p99, 2)} ms, "
                 f"frames/launch {r['mean_frames_per_launch']}, not submitted {r['not_submitted']}")
 
+    c5 = {}
+    if not a.no_batch and not a.no_frame:
+        c5 = c5_capacity(fv, torch, dev, stream, forms, a.batch_steps)
+
     if a.calib_copy_mb > 0:
         n = a.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -479,9 +528,12 @@ def main():
         result["serving"] = serving
     if sweep:
         result["serving_sweep"] = sweep
+    if c5:
+        result["c5_capacity_device_input"] = c5
     if not a.no_cpu_baseline:
         import oracle
         from oracle.metrics import errors
+        result["oracle_c1"] = oracle_c1()
         ref = oracle.encode_gmm(X, g)
         for f in forms:
             result["forms"][f]["error_vs_oracle"] = errors(outputs[f], ref)
