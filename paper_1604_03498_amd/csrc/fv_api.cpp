@@ -266,6 +266,25 @@ hipError_t run_sliced(const fv::Consts& c, int prec, const float* X, bool vec_ok
   }
 }
 
+hipError_t run_normext(const fv::Consts& c, int prec, const float* X, bool vec_ok, int64_t N, int P,
+                       const fv::Item* items, int n_items, int grid, const float2* lse,
+                       int64_t stride, float* partials, hipStream_t s) {
+  const fv::Frags16 fr = frags(c, prec);
+  switch (prec) {
+    case FV_PREC_FP32: return fv::launch_normext(c, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
+    case FV_PREC_BF16_SPLIT: return fv::launch_normext16_bf16s(c, fr, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
+    case FV_PREC_FP16_SPLIT: return fv::launch_normext16_f16s(c, fr, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
+    default: return fv::launch_normext16_bf16(c, fr, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
+  }
+}
+
+// Component groups per chunk of the group-wise second pass (its workgroups have Wg waves, or 4
+// when Wg = 8 and DP > 64).
+int normext_groups(const fv::Consts& c) {
+  const int w = (c.DP > 64 && c.Wg == 8) ? 4 : c.Wg;
+  return c.Kp / (fv::kCompsPerWave * w);
+}
+
 // Rows one second-pass workgroup consumes per round of its waves (32-row tiles).
 int sliced_round(const fv::Consts& c, int prec) {
   switch (prec) {
@@ -337,6 +356,15 @@ int split_single_chunk(int64_t N, int device, int slices, int round, int wgs_per
   const int64_t per = (N + target_chunks - 1) / target_chunks;
   const int64_t P = std::max<int64_t>(round, (per + round - 1) / round * round);
   return (int)std::min<int64_t>(P, (int64_t)1 << 20);
+}
+
+// Chunk length of the group-wise second pass for a single frame: about one workgroup per CU
+// over all (chunk, component group) pairs, in whole tiles.
+int normext_single_chunk(int64_t N, int device, int groups) {
+  const int64_t target = std::max<int64_t>(1, (device_cu_count(device) + groups - 1) / groups);
+  const int64_t tiles = (N + fv::kTile - 1) / fv::kTile;
+  const int64_t per = std::max<int64_t>(1, (tiles + target - 1) / target);
+  return (int)std::min<int64_t>(per * fv::kTile, (int64_t)1 << 20);
 }
 
 // Frame-relative chunk length of the batched path (a multiple of 128 rows): FV_BATCH_CHUNK
@@ -692,8 +720,12 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   const Path path = choose_single(gmm, N);
   const int slices = c.Kp / fv::kCompsPerWave;
   int P = fv::kTile;
+  // the two-pass path's second pass: component-sliced workgroups up to 256 components (more
+  // parallelism for one frame), whole component groups beyond
+  const bool grouped = c.Kp > fv::kFusedMaxK;
   if (N > 0)
     P = (path == Path::kFused) ? fused_single_chunk(N, gmm->device, c.Wg)
+        : grouped              ? normext_single_chunk(N, gmm->device, normext_groups(c))
                                : split_single_chunk(N, gmm->device, slices, sliced_round(c, precision),
                                                     precision == FV_PREC_FP32 ? 2 : 1);
   const int n_items = N > 0 ? (int)((N + P - 1) / P) : 0;
@@ -733,8 +765,12 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
         const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
         const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
         FV_HIP(run_lse(c, precision, Xd, vec_ok, N, n_tiles, grid1, lse, N, s));
-        FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
-                          partials, s));
+        if (grouped)
+          FV_HIP(run_normext(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse,
+                             N, partials, s));
+        else
+          FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
+                            partials, s));
       }
       timing_end(t0, 0, s);
     }
@@ -873,9 +909,9 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
         const int n_tiles = (int)((rows + fv::kTile - 1) / fv::kTile);
         const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
         FV_HIP(run_lse(c, precision, Xd, vec_ok, rows, n_tiles, grid1, lse, rows, s));
-        const int slices = c.Kp / fv::kCompsPerWave;
-        const int grid2 = xcd_grid(std::max(1, std::min(n_items, 2 * device_cu_count(gmm->device) / slices + 1)));
-        FV_HIP(run_sliced(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
+        const int groups = normext_groups(c);
+        const int grid2 = xcd_grid(std::max(1, std::min(n_items, (device_cu_count(gmm->device) + groups - 1) / groups)));
+        FV_HIP(run_normext(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
       }
       timing_end(t0, 0, s);
     }

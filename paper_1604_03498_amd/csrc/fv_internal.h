@@ -95,6 +95,14 @@ hipError_t launch_sliced(const Consts& c, int precision, const float* X, bool ve
                          int P, const Item* items, int n_items, int grid, const float2* lse,
                          int64_t lse_stride, float* partials, hipStream_t stream);
 
+// Second pass over whole component groups: grid = (grid, Kp / (32 * W)) workgroups of W waves
+// (W = Wg, or 4 when Wg = 8 and DP > 64), each owning a chunk of rows (work table or arithmetic,
+// as launch_stats) and one group of 32 * W components; gamma from the first pass's
+// normalisers.  Writes the group's columns of every item's partial slot.
+hipError_t launch_normext(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
+                          const Item* items, int n_items, int grid, const float2* lse,
+                          int64_t lse_stride, float* partials, hipStream_t stream);
+
 // Rows one workgroup of the second pass consumes per round (4 waves x 32-row tiles).
 int sliced_rows_per_wave_round();
 
@@ -133,6 +141,10 @@ struct Frags16 {
                                    bool vec_ok, int64_t N, int P, const Item* items,           \
                                    int n_items, int grid, const float2* lse,                   \
                                    int64_t lse_stride, float* partials, hipStream_t stream);   \
+  hipError_t launch_normext16_##sfx(const Consts& c, const Frags16& fr, const float* X,        \
+                                    bool vec_ok, int64_t N, int P, const Item* items,          \
+                                    int n_items, int grid, const float2* lse,                  \
+                                    int64_t lse_stride, float* partials, hipStream_t stream);  \
   int sliced16_waves_##sfx(int DP);
 FV_DECLARE_FORM(bf16s)
 FV_DECLARE_FORM(f16s)

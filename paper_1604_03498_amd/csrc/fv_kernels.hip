@@ -167,6 +167,151 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
   }
 }
 
+// Second pass over whole component groups (see normext16_kernel): the fused kernel's layout
+// (W waves x 32 components, a shared double-buffered tile), gamma from the first pass's
+// per-row normalisers, one barrier per tile.
+template <int DP, int W>
+__global__ __launch_bounds__(64 * W) void normext_f32_kernel(
+    const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
+    const Item* __restrict__ items, int n_items, const float2* __restrict__ lse, int G,
+    int64_t lse_stride, const float* __restrict__ A32, const float* __restrict__ c32, int Kp,
+    float* __restrict__ partials) {
+  constexpr int NT = 64 * W;
+  constexpr int NB = 2 * DP / 32;
+  using IO = TileIO<DP, NT>;
+  constexpr int XS = IO::XS;
+
+  __shared__ __attribute__((aligned(16))) float xs[2][kTile * XS];
+  __shared__ __attribute__((aligned(16))) float nrm[2][2 * kTile];  // per row: M, log2 Z
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int h = lane >> 5;
+  const int j = lane & 31;
+  const int comp = blockIdx.y * (W * kCompsPerWave) + w * kCompsPerWave + j;
+
+  float areg[DP];
+  load_areg<DP>(areg, A32, comp / kCompsPerWave, lane);
+  const float cval = c32[comp];
+  const size_t slot = (size_t)(2 * DP + 1) * Kp;
+
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    int64_t row0;
+    int nrows;
+    if (items != nullptr) {
+      const Item t = items[it];
+      row0 = t.row0;
+      nrows = t.nrows;
+    } else {
+      row0 = (int64_t)it * P;
+      const int64_t rem = N - row0;
+      nrows = (int)(rem < (int64_t)P ? rem : (int64_t)P);
+    }
+    const int ntiles = (nrows + kTile - 1) / kTile;
+    auto valid_of = [&](int t) {
+      const int v = nrows - t * kTile;
+      return v < kTile ? v : kTile;
+    };
+
+    f32x16 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
+    float s0 = 0.f;
+
+    f32x4 pre[IO::kPer];
+    float2 lv[kMaxLseGroups];
+    auto fetch = [&](int t) {
+      IO::fetch(pre, X, D, vec_ok != 0, row0 + (int64_t)t * kTile, valid_of(t), tid);
+      if (tid < kTile) fetch_lse(lv, lse, G, lse_stride, row0 + (int64_t)t * kTile + tid, tid < valid_of(t));
+    };
+    auto stage = [&](int buf, int t) {
+      IO::store(xs[buf], pre, tid);
+      if (tid < kTile) {
+        float M = 0.f, L2Z = INFINITY;  // rows past the tile end get gamma = 0
+        if (tid < valid_of(t)) merge_lse(lv, G, M, L2Z);
+        nrm[buf][2 * tid] = M;
+        nrm[buf][2 * tid + 1] = L2Z;
+      }
+    };
+    fetch(0);
+    stage(0, 0);
+    __syncthreads();
+
+    for (int t = 0; t < ntiles; ++t) {
+      const int buf = t & 1;
+      const bool has_next = (t + 1) < ntiles;
+      if (has_next) fetch(t + 1);
+      const float* xb = xs[buf];
+
+      f32x16 hi, lo;
+      estep_f32<DP>(xb + j * XS + DP * h, areg, cval, hi, lo);
+      f32x16 gam;
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(&nrm[buf][2 * (8 * qq + 4 * h)]);
+        const f32x4 b = *reinterpret_cast<const f32x4*>(&nrm[buf][2 * (8 * qq + 4 * h) + 4]);
+        const float Ms[4] = {a[0], a[2], b[0], b[2]};
+        const float Ls[4] = {a[1], a[3], b[1], b[3]};
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int r = 4 * qq + p;
+          gam[r] = fast_exp2(((hi[r] - Ms[p]) + lo[r]) - Ls[p]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s0 += gam[r];
+      stats_f32<DP>(xb, h, j, gam, acc);
+
+      if (has_next) stage(buf ^ 1, t + 1);
+      __syncthreads();
+    }
+
+    __amdgpu_buffer_rsrc_t rs = make_rsrc(partials + (size_t)it * slot,
+                                          (uint32_t)(slot * sizeof(float)));
+    const int vrow = comp * 4 + 4 * h * Kp * 4;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[b][r]), rs, vrow,
+                                              (32 * b + crow(r, 0)) * Kp * 4, 0);
+    auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(s0), __float_as_uint(s0), false,
+                                              false);
+    const float s0_total = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    if (h == 0)
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s0_total), rs, comp * 4,
+                                            2 * DP * Kp * 4, 0);
+  }
+}
+
+template <int DP, int W>
+hipError_t launch_normext_dp(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
+                             const Item* items, int n_items, int grid, const float2* lse,
+                             int64_t lse_stride, float* partials, hipStream_t stream) {
+  hipLaunchKernelGGL((normext_f32_kernel<DP, W>), dim3(grid, c.Kp / (kCompsPerWave * W)), dim3(64 * W), 0,
+                     stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c),
+                     lse_stride, c.A32, c.c32, c.Kp, partials);
+  return hipGetLastError();
+}
+
+template <int W>
+hipError_t normext_dp(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
+                      const Item* items, int n_items, int grid, const float2* lse,
+                      int64_t lse_stride, float* partials, hipStream_t stream) {
+  switch (c.DP) {
+    case 16: return launch_normext_dp<16, W>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    case 32: return launch_normext_dp<32, W>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    case 48: return launch_normext_dp<48, W>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    case 64: return launch_normext_dp<64, W>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    case 80: return launch_normext_dp<80, W>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    case 96: return launch_normext_dp<96, W>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int DP, int W, bool LSE>
 hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
                         const Item* items, int n_items, int grid, int groups, float* partials,
@@ -228,6 +373,21 @@ hipError_t launch_lse(const Consts& c, int precision, const float* X, bool vec_o
   if (precision != 0) return hipErrorNotSupported;
   return dispatch_w<true>(c.Wg, c, X, vec_ok, N, kTile, items, n_items, grid, lse_groups(c),
                           nullptr, lse, lse_stride, stream);
+}
+
+hipError_t launch_normext(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
+                          const Item* items, int n_items, int grid, const float2* lse,
+                          int64_t lse_stride, float* partials, hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  // above DP = 64 an 8-wave workgroup (two waves per SIMD) runs out of registers: use 4 waves
+  // (128 components per workgroup, Kp / 128 of them per chunk)
+  switch (c.DP > 64 && c.Wg == 8 ? 4 : c.Wg) {
+    case 1: return normext_dp<1>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    case 2: return normext_dp<2>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    case 4: return normext_dp<4>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    case 8: return normext_dp<8>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    default: return hipErrorNotSupported;
+  }
 }
 
 }  // namespace fv
