@@ -237,7 +237,7 @@ def roofline(form, K, D, ndesc, stats_avg_ms, path, launches_per_step=1):
 
 
 def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_streams=2,
-                rate_mult=1.0):
+                rate_mult=1.0, device_input=False):
     """Open-loop serving run: 16 camera streams, Poisson arrivals at 30 Hz each, frames of
     8,000-32,000 descriptors (320x240 .. 640x480), D = 80, K = 512.  Latency is measured from
     each frame's scheduled arrival time to the completion of its encode (so a late submit
@@ -249,12 +249,17 @@ def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_
                                          pool=pool)
     frames = {(st, p): fvsynth.frame(g, sizes[st], 100000 + 100 * st + p, 0.05)
               for st in range(len(sizes)) for p in range(pool)}
+    if device_input:  # frames already resident in HBM: no staging copy at submit time
+        import torch
+        frames = {k: torch.from_numpy(v).cuda() for k, v in frames.items()}
+        torch.cuda.synchronize()
+    submit = (lambda s_, X: s_.try_submit_device(X)) if device_input else (lambda s_, X: s_.try_submit(X))
     h = fv.gmm_load(g.weights, g.means, g.variances, device=0)
     cfg = fv.server_config(precision=PREC_CODE[form], n_streams=n_streams,
                            hbm_budget_bytes=int(budget_bytes))
     srv = fv.Server(h, cfg)
     for st in range(len(sizes)):          # warm every frame size once (buffers, code objects)
-        t = srv.submit(frames[(st, 0)])
+        t = submit(srv, frames[(st, 0)])[1]
         while srv.next_done(1000.0) != t:
             pass
         srv.poll(t, want_out=False)
@@ -288,7 +293,7 @@ def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_
             dropped += 1
             continue
         while True:
-            rc, tk = srv.try_submit(frames[(st, p)])
+            rc, tk = submit(srv, frames[(st, p)])
             if rc == fv.OK:
                 break
             time.sleep(0.0005)
@@ -329,7 +334,9 @@ def run_serving(fv, seconds, warm_s, budget_bytes, form="bf16_split", pool=2, n_
             "gpu_busy_fraction": stats["busy_s"] / max(wall - warm_s, 1e-9), "n_streams": n_streams,
             "busy_note": "sum of launch durations over the server's streams / wall time (can exceed 1 "
                          "when launches on different streams overlap)",
-            "input": "host memory (submit copies into pinned staging; H2D inside the launch)"}
+            "input": ("device memory (fv_server_submit_device; device-to-device gather in the launch)"
+                      if device_input else
+                      "host memory (submit copies into pinned staging; H2D inside the launch)")}
 
 
 def c5_capacity(fv, torch, dev, stream, forms, steps):
@@ -480,18 +487,19 @@ def main():
                 f"{r['latency_ms_from_arrival']['p99']:.3f} ms, {r['throughput_desc_per_s']:.3e} desc/s")
             serving.append(r)
     sweep = []
-    if a.serving_seconds > 0 and a.sweep:
-        for mult in [float(x) for x in a.sweep.split(",") if x]:
-            log(f"[bench] serving sweep x{mult:g} (budget 2048 MiB, 2 s)")
-            r = run_serving(fv, 2.0, 0.5, 2 << 30, rate_mult=mult)
-            sweep.append({k: r[k] for k in ("rate_hz_per_stream", "offered_desc_per_s",
-                                             "throughput_desc_per_s", "latency_ms_from_arrival",
-                                             "mean_frames_per_launch", "gpu_busy_fraction",
-                                             "frames", "failed", "not_submitted")})
-            p99 = r["latency_ms_from_arrival"]["p99"]
-            log(f"[bench]   offered {r['offered_desc_per_s']:.3e}, served {r['throughput_desc_per_s']:.3e} "
-                f"desc/s, p99 {p99 if p99 is None else round(p99, 2)} ms, "
-                f"frames/launch {r['mean_frames_per_launch']}, not submitted {r['not_submitted']}")
+    mults = [float(x) for x in a.sweep.split(",") if x] if a.serving_seconds > 0 else []
+    for dev_in, mult in [(d, m) for d in (False, True) for m in mults]:
+        log(f"[bench] serving sweep x{mult:g} ({'device' if dev_in else 'host'} input, "
+            f"budget 2048 MiB, 2 s)")
+        r = run_serving(fv, 2.0, 0.5, 2 << 30, rate_mult=mult, device_input=dev_in)
+        sweep.append({k: r[k] for k in ("rate_hz_per_stream", "offered_desc_per_s",
+                                         "throughput_desc_per_s", "latency_ms_from_arrival",
+                                         "mean_frames_per_launch", "gpu_busy_fraction",
+                                         "frames", "failed", "not_submitted", "input")})
+        p99 = r["latency_ms_from_arrival"]["p99"]
+        log(f"[bench]   offered {r['offered_desc_per_s']:.3e}, served {r['throughput_desc_per_s']:.3e} "
+            f"desc/s, p99 {p99 if p99 is None else round(p99, 2)} ms, "
+            f"frames/launch {r['mean_frames_per_launch']}, not submitted {r['not_submitted']}")
 
     c5 = {}
     if not a.no_batch and not a.no_frame:

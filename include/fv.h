@@ -210,6 +210,12 @@ int fv_server_destroy(fv_server* srv);
  * fit the budget, FV_E_AGAIN if the queue is full, FV_E_INVAL for bad arguments. */
 int fv_server_submit(fv_server* srv, const float* X, int64_t N, uint64_t* ticket);
 
+/* As fv_server_submit for a frame already in device memory: X [N x D] f32 row-major on the
+ * server's GPU.  Nothing is copied at submit time; the launch gathers the frame with a
+ * device-to-device copy, so the caller keeps X valid and unmodified until the ticket has
+ * finished (fv_server_poll returned something other than FV_PENDING).  Same return codes. */
+int fv_server_submit_device(fv_server* srv, const float* X, int64_t N, uint64_t* ticket);
+
 /* Result of a ticket: FV_PENDING while queued or running; FV_OK with out (host, 2*K*D floats,
  * may be NULL) and st (may be NULL) filled -- the ticket is then consumed; a failure code
  * (FV_E_TIMEOUT, FV_E_DEVICE) also consumes it; FV_E_NOTFOUND for an unknown ticket. */

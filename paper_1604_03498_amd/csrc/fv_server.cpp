@@ -84,8 +84,9 @@ class HostPool {
 struct Request {
   uint64_t ticket = 0;
   int64_t rows = 0;
-  float* xin = nullptr;
+  float* xin = nullptr;          // pinned staging copy of a host frame
   size_t xin_cls = 0;
+  const float* xdev = nullptr;   // or the caller's device-resident frame (not owned)
   float* out = nullptr;
   size_t out_cls = 0;
   double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
@@ -199,11 +200,13 @@ int launch(fv_server* s, Lane& L) {
     if (hipMalloc(&L.dOut, cap * 4) != hipSuccess) return FV_E_NOMEM;
     L.dOut_cap = cap;
   }
-  for (int b = 0; b < B; ++b)
-    if (L.batch[b]->rows > 0 &&
-        hipMemcpyAsync(L.dX + (size_t)off[b] * D, L.batch[b]->xin, (size_t)L.batch[b]->rows * D * 4,
-                       hipMemcpyHostToDevice, L.stream) != hipSuccess)
+  for (int b = 0; b < B; ++b) {
+    const Request* r = L.batch[b];
+    if (r->rows > 0 &&
+        hipMemcpyAsync(L.dX + (size_t)off[b] * D, r->xdev ? r->xdev : r->xin, (size_t)r->rows * D * 4,
+                       r->xdev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, L.stream) != hipSuccess)
       return FV_E_DEVICE;
+  }
   const unsigned fl = FV_X_DEVICE | FV_OUT_DEVICE | FV_ASYNC |
                       (s->cfg.flags & (FV_NO_POWER_NORM | FV_NO_L2_NORM));
   int rc = fv_encode_batch(s->gmm, L.dX, off.data(), B, L.dOut, s->cfg.precision, fl, L.stream);
@@ -436,7 +439,9 @@ int fv_server_destroy(fv_server* s) {
   return rc;
 }
 
-int fv_server_submit(fv_server* s, const float* X, int64_t N, uint64_t* ticket) {
+namespace {
+
+int submit_impl(fv_server* s, const float* X, int64_t N, uint64_t* ticket, bool device) {
   if (!s || !ticket || N < 0 || (N > 0 && !X)) return FV_E_INVAL;
   const std::vector<int64_t> one{N};
   if (s->cfg.hbm_budget_bytes > 0 && footprint(s, one) > s->cfg.hbm_budget_bytes) {
@@ -454,7 +459,9 @@ int fv_server_submit(fv_server* s, const float* X, int64_t N, uint64_t* ticket) 
   std::unique_ptr<Request> r(new (std::nothrow) Request());
   if (!r) return FV_E_NOMEM;
   r->rows = N;
-  if (N > 0) {
+  if (N > 0 && device) {
+    r->xdev = X;
+  } else if (N > 0) {
     r->xin = static_cast<float*>(s->pool->get((size_t)N * s->D * 4, &r->xin_cls));
     if (!r->xin) return FV_E_NOMEM;
     std::memcpy(r->xin, X, (size_t)N * s->D * 4);
@@ -475,6 +482,16 @@ int fv_server_submit(fv_server* s, const float* X, int64_t N, uint64_t* ticket) 
   }
   s->cv_work.notify_one();
   return FV_OK;
+}
+
+}  // namespace
+
+int fv_server_submit(fv_server* s, const float* X, int64_t N, uint64_t* ticket) {
+  return submit_impl(s, X, N, ticket, false);
+}
+
+int fv_server_submit_device(fv_server* s, const float* X, int64_t N, uint64_t* ticket) {
+  return submit_impl(s, X, N, ticket, true);
 }
 
 int fv_server_poll(fv_server* s, uint64_t ticket, float* out, fv_req_stats* st) {

@@ -20,7 +20,8 @@ X_DEVICE, OUT_DEVICE, NO_POWER_NORM, NO_L2_NORM, ASYNC = 1, 2, 4, 8, 16
 EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "fv_encode",
                     "fv_encode_batch", "fv_gmm_set_tuning", "fv_gmm_get_tuning",
                     "fv_kernel_timing", "fv_kernel_timing_read", "fv_server_config_default", "fv_server_create", "fv_server_destroy",
-                    "fv_server_submit", "fv_server_poll", "fv_server_next_done",
+                    "fv_server_submit", "fv_server_submit_device", "fv_server_poll",
+                    "fv_server_next_done",
                     "fv_server_get_stats", "fv_strerror", "fv_last_device_error")
 EXEC_HIP, EXEC_FAKE = 0, 1
 
@@ -100,11 +101,13 @@ def load():
     lib.fv_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.fv_server_destroy.argtypes = [vp]
     lib.fv_server_submit.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.fv_server_submit_device.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
     lib.fv_server_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(ReqStats)]
     lib.fv_server_next_done.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
     lib.fv_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats), i32]
     for f in (lib.fv_server_create, lib.fv_server_destroy, lib.fv_server_submit,
-              lib.fv_server_poll, lib.fv_server_next_done, lib.fv_server_get_stats):
+              lib.fv_server_submit_device, lib.fv_server_poll, lib.fv_server_next_done,
+              lib.fv_server_get_stats):
         f.restype = i32
     lib.fv_strerror.argtypes = [i32]
     lib.fv_strerror.restype = ctypes.c_char_p
@@ -328,6 +331,7 @@ class Server:
         self.gmm = g
         self.out_len = g.out_len if g else 2 * cfg.fake_K * cfg.fake_D
         self.D = g.D if g else cfg.fake_D
+        self._device_inputs = {}  # ticket -> frame kept alive until the ticket finishes
 
     def submit(self, X) -> int:
         Xn = _host_f32(X)
@@ -348,6 +352,35 @@ class Server:
                                      int(Xn.shape[0]), ctypes.byref(t))
         return rc, (t.value if rc == OK else None)
 
+    def try_submit_device(self, X):
+        """fv_server_submit_device for a contiguous float32 [N, D] tensor in device memory (a
+        torch CUDA tensor; the fake executor also takes a numpy array).  (code, ticket or None);
+        the tensor is kept referenced until the ticket finishes."""
+        if _is_torch(X):
+            if X.dtype.itemsize != 4 or not X.is_contiguous() or X.dim() != 2:
+                raise ValueError("X must be a contiguous float32 [N, D] tensor")
+            n, d, ptr = int(X.shape[0]), int(X.shape[1]), X.data_ptr()
+        else:
+            Xn = np.ascontiguousarray(X, dtype=np.float32)
+            if Xn is not X:
+                X = Xn
+            n, d, ptr = int(Xn.shape[0]), int(Xn.shape[1]), Xn.ctypes.data
+        if d != self.D:
+            raise ValueError("X must be [N, D]")
+        t = ctypes.c_uint64()
+        rc = load().fv_server_submit_device(ctypes.c_void_p(self.handle), ctypes.c_void_p(ptr), n,
+                                            ctypes.byref(t))
+        if rc != OK:
+            return rc, None
+        self._device_inputs[t.value] = X
+        return rc, t.value
+
+    def submit_device(self, X) -> int:
+        rc, t = self.try_submit_device(X)
+        if rc != OK:
+            raise FvError(rc, "fv_server_submit_device")
+        return t
+
     def poll(self, ticket: int, want_out: bool = True):
         """(code, out or None, stats dict or None)."""
         out = np.empty(self.out_len, np.float32) if want_out else None
@@ -357,6 +390,7 @@ class Server:
                                    ctypes.byref(st))
         if rc == PENDING or rc == E_NOTFOUND:
             return rc, None, None
+        self._device_inputs.pop(ticket, None)
         stats = {f: getattr(st, f) for f, _ in ReqStats._fields_}
         return rc, (out if rc == OK else None), stats
 
@@ -378,6 +412,7 @@ class Server:
         if self.handle:
             _check(load().fv_server_destroy(ctypes.c_void_p(self.handle)), "fv_server_destroy")
             self.handle = 0
+            self._device_inputs.clear()  # destroy has waited for every launch
 
     def __enter__(self):
         return self

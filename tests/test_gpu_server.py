@@ -108,3 +108,32 @@ def test_small_budget_forces_queueing(fv):
         assert rc == fv.OK
         e = errors(out, oracle.encode_gmm(frames[i], g))
         assert e["e_inf"] <= 1e-5 and e["e_2"] <= 1e-5
+
+
+def test_device_submission_matches_host_submission(fv):
+    import torch
+    say("[gpu] server device-resident frames, bf16 split K=512 D=80")
+    g = fvsynth.gmm(512, 80, 0)
+    sizes = [8000, 123, 12500, 0, 2048]
+    frames = [fvsynth.frame(g, n, 700 + i, 0.05) for i, n in enumerate(sizes)]
+    dev = [torch.from_numpy(X).cuda() for X in frames]
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    cfg = fv.server_config(precision=fv.PREC_BF16_SPLIT, n_streams=2)
+    with fv.Server(h, cfg) as s:
+        host = drain(s, [s.submit(X) for X in frames])
+        host = [host[t] for t in sorted(host)]
+    with fv.Server(h, cfg) as s:
+        tickets = [s.submit_device(Xd) for Xd in dev]
+        res = drain(s, tickets)
+        assert not s._device_inputs
+    for i, t in enumerate(tickets):
+        rc, out, st = res[t]
+        assert rc == fv.OK and host[i][0] == fv.OK
+        # frame-relative chunking: bitwise equal whatever launches the frames shared
+        assert np.array_equal(out, host[i][1]), f"frame {i} differs from the host submission"
+        if sizes[i] == 0:
+            assert np.all(out == 0)
+            continue
+        e = errors(out, oracle.encode_gmm(frames[i], g))
+        say(f"  frame {i} N={sizes[i]} e_inf={e['e_inf']:.2e}")
+        assert e["e_inf"] <= 1e-3 and e["e_2"] <= 1e-3

@@ -145,3 +145,17 @@ def test_batching_window_collects_frames():
         res = drain(s, tickets)
         assert all(res[t][0] == fv.OK and res[t][2]["batch_frames"] == 5 for t in tickets)
         assert res[tickets[0]][2]["t_admit_us"] - res[tickets[0]][2]["t_submit_us"] >= 0.9e5
+
+
+def test_device_submission_keeps_frame_until_done():
+    # the fake executor never reads X; the binding must keep the frame referenced until the
+    # ticket has finished, then release it
+    with fake(n_streams=1) as s:
+        X = np.ones((500, D), np.float32)
+        t = s.submit_device(X)
+        assert t in s._device_inputs
+        res = drain(s, [t])
+        assert res[t][0] == fv.OK and res[t][2]["rows"] == 500
+        assert t not in s._device_inputs
+        with pytest.raises(ValueError):
+            s.submit_device(np.ones((5, D + 1), np.float32))
