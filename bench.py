@@ -44,10 +44,10 @@ TRAFFIC_JSON = os.path.join(HERE, "profiles", "hbm_traffic.json")
 STATS_KERNELS = {
     ("fp32", "split"): ["fused_f32_kernel<64, 8, true>", "sliced_f32_kernel<64>"],
     ("fp32", "fused"): ["fused_f32_kernel<64, 8, false>"],
-    ("bf16_split", "split"): ["fused16_kernel<64, 8, true>", "sliced16_kernel<64>"],
-    ("bf16_split", "fused"): ["fused16_kernel<64, 8, false>"],
-    ("fp16_split", "split"): ["fused16_kernel<64, 8, true>", "sliced16_kernel<64>"],
-    ("fp16_split", "fused"): ["fused16_kernel<64, 8, false>"],
+    ("bf16_split", "split"): ["lse16_kernel<64, 8>", "sliced16_kernel<64>"],
+    ("bf16_split", "fused"): ["fused16t_kernel<64, 8>"],
+    ("fp16_split", "split"): ["lse16_kernel<64, 8>", "sliced16_kernel<64>"],
+    ("fp16_split", "fused"): ["fused16t_kernel<64, 8>"],
 }
 
 
