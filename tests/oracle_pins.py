@@ -15,6 +15,9 @@ raises AssertionError when the oracle disagrees with the fact it checks.  The fa
   not print
 * translation, scaling, negation, component / descriptor permutation, duplication
 * ||phi||_2 == 1 after L2; N = 0 and phi == 0 give zeros                         (definition)
+* with the posterior threshold tau (Algorithm 1's test), U and V == the autograd
+  per-descriptor gradients summed over the (t, k) whose torch posterior exceeds tau
+                                                                                 (library)
 """
 from __future__ import annotations
 
@@ -98,6 +101,48 @@ def pin_gradient_autograd(o, seed=1):
         for got, ref in ((U, U_ref), (V, V_ref)):
             err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
             assert err < 1e-11, err
+
+
+def pin_threshold_autograd(o, seed=5, tau=1e-6):
+    """Threshold mode against per-descriptor gradients: the (t, k) term of U (V) is the
+    gradient of log p(x_t) with respect to mu_k (sigma_k) times sigma_k; the term enters only
+    when the posterior of k given x_t, from torch's log densities, exceeds tau."""
+    import torch
+    from torch.distributions import Categorical, Independent, MixtureSameFamily, Normal
+    rng = np.random.default_rng(seed)
+    K, D, N = 6, 4, 120
+    w = rng.dirichlet(np.ones(K) * 2).astype(np.float32)
+    mu = (rng.standard_normal((K, D)) * 2.5).astype(np.float32)
+    var = rng.uniform(0.4, 1.2, (K, D)).astype(np.float32)
+    X = (mu[rng.integers(0, K, N)] + rng.standard_normal((N, D)) * 0.8).astype(np.float32)
+    X64 = torch.tensor(X.astype(np.float64))
+    w_t = torch.tensor(w.astype(np.float64))
+    mu0 = torch.tensor(mu.astype(np.float64))
+    sd0 = torch.tensor(np.sqrt(var.astype(np.float64)))
+
+    def per_desc(m, s):
+        return MixtureSameFamily(Categorical(probs=w_t), Independent(Normal(m, s), 1)).log_prob(X64)
+
+    Jm, Js = torch.autograd.functional.jacobian(per_desc, (mu0, sd0))  # [N, K, D] each
+    comp = Independent(Normal(mu0, sd0), 1).log_prob(X64[:, None, :]) + torch.log(w_t)
+    post = torch.softmax(comp, dim=1).numpy()
+    # every decision is far from the boundary, and the threshold removes some terms
+    assert np.min(np.abs(np.log(post) - np.log(tau))) > 1e-3
+    keep = post > tau
+    assert 0 < np.count_nonzero(~keep) < keep.size // 2
+    sd = sd0.numpy()
+    U_ref = sd * np.einsum("tk,tkd->kd", keep, Jm.numpy())
+    V_ref = sd * np.einsum("tk,tkd->kd", keep, Js.numpy())
+    phi = o.encode(X, w, mu, var, flags=RAW, tau=tau)
+    w64 = w.astype(np.float64)[:, None]
+    U = phi[:K * D].reshape(K, D) * N * np.sqrt(w64)
+    V = phi[K * D:].reshape(K, D) * N * np.sqrt(2 * w64)
+    for got, ref in ((U, U_ref), (V, V_ref)):
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert err < 1e-11, err
+    # and the dropped terms are not negligible at this precision
+    full = o.encode(X, w, mu, var, flags=RAW)
+    assert np.max(np.abs(full - phi)) > 1e-9 * np.max(np.abs(full))
 
 
 def pin_single_component(o, seed=2):
@@ -219,4 +264,4 @@ def pin_normalisation(o, seed=4):
 
 ALL_PINS = (pin_posteriors_sklearn, pin_posteriors_logistic, pin_gradient_autograd,
             pin_single_component, pin_on_means, pin_unit_variance, pin_invariances,
-            pin_normalisation)
+            pin_normalisation, pin_threshold_autograd)

@@ -85,6 +85,10 @@ MUTANTS = {
     "no_division_by_N": ("double cu = 1.0 / ((double)N * sqrt",
                          "double cu = 1.0 / ((double)1 * sqrt"),
     "l1_instead_of_l2": ("ss += out[i] * out[i];", "ss += fabs(out[i]);"),
+    "threshold_inverted": ("if (tau >= 0.0 && !(g > tau)) continue;",
+                           "if (tau >= 0.0 && (g > tau)) continue;"),
+    "threshold_ignored": ("if (tau >= 0.0 && !(g > tau)) continue;",
+                          "if (tau > 1e300 && !(g > tau)) continue;"),
     "unsigned_sqrt": ("out[i] = (p > 0.0) ? sqrt(p) : ((p < 0.0) ? -sqrt(-p) : 0.0);",
                       "out[i] = sqrt(fabs(p));"),
 }
