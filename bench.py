@@ -158,6 +158,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch with the default tuning instead of the measuring autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-mode", action="store_true",
+                    help="skip the posterior-threshold (paper mode) measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="measured seconds of each open-loop serving run (0: skip)")
@@ -181,14 +183,16 @@ def path_of(K, N, n_cu, fv_path_env):
     return "split" if N < 4 * 32 * n_cu else "fused"
 
 
-def time_form(fv, torch, h, Xd, off, out, form, steps, warmup, stream, lat_samples, batch):
+def time_form(fv, torch, h, Xd, off, out, form, steps, warmup, stream, lat_samples, batch,
+              flags=0):
     prec = PREC_CODE[form]
+    fl = fv.ASYNC | flags
 
     def step():
         if batch:
-            fv.encode_batch(h, Xd, off, out=out, precision=prec, flags=fv.ASYNC, stream=stream)
+            fv.encode_batch(h, Xd, off, out=out, precision=prec, flags=fl, stream=stream)
         else:
-            fv.encode(h, Xd, out=out, precision=prec, flags=fv.ASYNC, stream=stream)
+            fv.encode(h, Xd, out=out, precision=prec, flags=fl, stream=stream)
 
     for _ in range(warmup):
         step()
@@ -478,6 +482,40 @@ def main():
         batch["config"] = {"workload": "c4_batch64_k256_d64", "frames": int(offb.size - 1),
                            "descriptors": int(offb[-1])}
 
+    # The paper's posterior threshold (gamma > 1e-6, skipped MFMA steps): the same frame, the
+    # same frame with its rows grouped by generating component, and the batch
+    paper = {}
+    paper_out = {}
+    if not a.no_paper_mode and not a.no_frame:
+        Xc = fvsynth.frame(g, N, fvsynth.WORKLOADS["c2_frame_k256_d64_n8000"]["frame_seed"], 0.05,
+                           clustered=True)
+        Xcd = torch.from_numpy(Xc).to(dev)
+        for form in forms:
+            paper[form] = {}
+            for name, xin in (("frame", Xd), ("frame_clustered", Xcd)):
+                out = torch.empty(2 * K * D, dtype=torch.float32, device=dev)
+                el, st_avg, _, _, _ = time_form(fv, torch, h, xin, off, out, form, a.steps,
+                                                a.warmup, stream, 0, False, fv.THRESHOLD)
+                paper[form][name] = {"value": N * a.steps / el, "ms_per_step": el * 1e3 / a.steps,
+                                     "stats_avg_us": round(st_avg * 1e3, 3)}
+                paper_out[(form, name)] = out.cpu().numpy()
+                log(f"[bench] paper mode {name} form={form}: {N * a.steps / el:.4e} desc/s, "
+                    f"stats {st_avg * 1e3:.3f} us")
+            if batch and form in batch:
+                outb = torch.empty(offb.size - 1, 2 * K * D, dtype=torch.float32, device=dev)
+                fv.set_tuning(hb, batch_path=1 if batch[form]["tuned"]["path"] == "fused" else 2,
+                              batch_chunk=batch[form]["tuned"]["chunk"])
+                el, st_avg, _, _, _ = time_form(fv, torch, hb, Xbd, offb, outb, form,
+                                                a.batch_steps, 2, stream, 0, True, fv.THRESHOLD)
+                nb = int(offb[-1])
+                paper[form]["batch"] = {"value": nb * a.batch_steps / el,
+                                        "ms_per_step": el * 1e3 / a.batch_steps,
+                                        "stats_avg_us": round(st_avg * 1e3, 3),
+                                        "path": batch[form]["tuned"]["path"]}
+                log(f"[bench] paper mode batch form={form}: {nb * a.batch_steps / el:.4e} desc/s")
+        if batch:
+            fv.set_tuning(hb)
+
     serving = []
     if a.serving_seconds > 0:
         for budget in (2 << 30, 64 << 20):
@@ -538,6 +576,11 @@ def main():
         result["serving_sweep"] = sweep
     if c5:
         result["c5_capacity_device_input"] = c5
+    if paper:
+        result["paper_threshold_mode"] = {
+            "tau": fv.THRESHOLD_TAU, "forms": paper,
+            "note": "terms with posterior <= tau left out; MFMA steps with no term above tau "
+                    "skipped; frame_clustered = the same descriptors grouped by component"}
     if not a.no_cpu_baseline:
         import oracle
         from oracle.metrics import errors
@@ -545,6 +588,13 @@ def main():
         ref = oracle.encode_gmm(X, g)
         for f in forms:
             result["forms"][f]["error_vs_oracle"] = errors(outputs[f], ref)
+        if paper:
+            ref_t = oracle.encode_gmm(X, g, tau=fv.THRESHOLD_TAU)
+            ref_tc = oracle.encode_gmm(Xc, g, tau=fv.THRESHOLD_TAU)
+            for f in forms:
+                paper[f]["frame"]["error_vs_oracle"] = errors(paper_out[(f, "frame")], ref_t)
+                paper[f]["frame_clustered"]["error_vs_oracle"] = errors(
+                    paper_out[(f, "frame_clustered")], ref_tc)
         result["cpu_baseline"] = cpu_baseline(g, [X], a.cpu_seconds)
     print(json.dumps(result), flush=True)
 

@@ -5,7 +5,9 @@
   float32 arrays *are* the model.  The float64 weights are kept only for sampling labels.
 * frame(g, N, seed, outlier_frac): rng = default_rng(seed); labels ~ Cat(weights64);
   x = mean[label] + sqrt(var[label]) * z, z ~ N(0, I); then round(outlier_frac*N) rows,
-  chosen without replacement, are replaced by U[-4, 4]^D.  Cast to float32.
+  chosen without replacement, are replaced by U[-4, 4]^D.  Cast to float32.  With
+  clustered=True the rows are then stably reordered by label (a frame whose neighbouring
+  descriptors come from the same component, as neighbouring patches of one region do).
 * batch_sizes(B, seed=1, lo=2000, hi=20000): default_rng(seed).integers(lo, hi+1, B).
 * serving_plan(...): 16 streams, Poisson arrivals at a rate per stream, resolutions
   assigned round-robin from 320x240 .. 640x480, N = 8000 * area / (320*240).
@@ -43,7 +45,8 @@ def gmm(K: int, D: int, seed: int = 0) -> Gmm:
                variances=var.astype(np.float32), weights64=w64)
 
 
-def frame(g: Gmm, N: int, seed: int, outlier_frac: float = 0.0) -> np.ndarray:
+def frame(g: Gmm, N: int, seed: int, outlier_frac: float = 0.0,
+          clustered: bool = False) -> np.ndarray:
     rng = np.random.default_rng(seed)
     K, D = g.K, g.D
     labels = rng.choice(K, size=N, p=g.weights64 / g.weights64.sum())
@@ -55,6 +58,8 @@ def frame(g: Gmm, N: int, seed: int, outlier_frac: float = 0.0) -> np.ndarray:
     if n_out > 0:
         rows = rng.choice(N, size=n_out, replace=False)
         x[rows] = rng.uniform(-4.0, 4.0, (n_out, D))
+    if clustered:
+        x = x[np.argsort(labels, kind="stable")]
     return np.ascontiguousarray(x.astype(np.float32))
 
 

@@ -18,8 +18,12 @@
  *   unless FV_NO_POWER_NORM: phi_i <- sign(phi_i) sqrt(|phi_i|)
  *   unless FV_NO_L2_NORM:    phi   <- phi / ||phi||_2  (left unscaled when the norm is 0)
  *
- * No posterior threshold is applied (every term is accumulated).  A frame with N = 0 encodes
- * to 2KD zeros.  Non-finite descriptor values are not checked: NaN propagates to the output.
+ * No posterior threshold is applied (every term is accumulated) unless FV_THRESHOLD asks for
+ * the paper's mode: a term (t, k) then enters u, v (and the gamma sum inside v) only if
+ * gamma_tk > FV_THRESHOLD_TAU (Algorithm 1's test), and groups of MFMA steps whose terms all
+ * fall below it are skipped (the paper's early termination of Phase 2, Sec. 3.3).  A frame with
+ * N = 0 encodes to 2KD zeros.  Non-finite descriptor values are not checked: NaN propagates to
+ * the output.
  *
  * Return codes: FV_OK (0), FV_PENDING (1), or a negative FV_E_* code; fv_strerror() names
  * them.  No C++ exception crosses this interface.  Functions are thread-safe unless stated.
@@ -58,6 +62,8 @@ extern "C" {
 #define FV_NO_POWER_NORM 4u   /* skip the signed square root */
 #define FV_NO_L2_NORM 8u      /* skip the L2 normalisation */
 #define FV_ASYNC 16u          /* return after enqueueing on the stream, without waiting */
+#define FV_THRESHOLD 32u      /* the paper's posterior threshold (see above) */
+#define FV_THRESHOLD_TAU 1e-6 /* its value: terms with gamma <= 1e-6 are left out */
 
 typedef struct fv_gmm fv_gmm;
 
@@ -92,6 +98,7 @@ int fv_gmm_info(const fv_gmm* gmm, int* K, int* D, int* device);
  * Encode one frame: X [N x D] float32 row-major -> out [2*K*D] float32, laid out as above.
  *   flags      FV_X_DEVICE / FV_OUT_DEVICE say where X and out live (host otherwise);
  *              FV_NO_POWER_NORM / FV_NO_L2_NORM drop the normalisation steps;
+ *              FV_THRESHOLD leaves out terms with gamma <= FV_THRESHOLD_TAU;
  *              FV_ASYNC returns once the work is enqueued on `hip_stream` -- the caller then
  *              keeps X and out alive (host buffers too) until that stream is synchronised.
  *   hip_stream a hipStream_t (NULL = the default stream) on the handle's device.
@@ -161,7 +168,7 @@ typedef struct fv_server fv_server;
 typedef struct fv_server_config {
   size_t hbm_budget_bytes;  /* device bytes in-flight batches may hold (0 = unlimited) */
   int precision;            /* FV_PREC_* */
-  unsigned flags;           /* FV_NO_POWER_NORM / FV_NO_L2_NORM only */
+  unsigned flags;           /* FV_NO_POWER_NORM / FV_NO_L2_NORM / FV_THRESHOLD only */
   int max_queue;            /* requests waiting for admission (<= 0: 4096) */
   int n_streams;            /* concurrent launches (<= 0: 2) */
   int max_batch_frames;     /* frames per launch (<= 0: 64) */

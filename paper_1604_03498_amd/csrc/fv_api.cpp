@@ -23,7 +23,16 @@ namespace {
 thread_local int t_last_hip_error = 0;
 
 constexpr unsigned kAllFlags =
-    FV_X_DEVICE | FV_OUT_DEVICE | FV_NO_POWER_NORM | FV_NO_L2_NORM | FV_ASYNC;
+    FV_X_DEVICE | FV_OUT_DEVICE | FV_NO_POWER_NORM | FV_NO_L2_NORM | FV_ASYNC | FV_THRESHOLD;
+// flags that change what a captured sequence computes
+constexpr unsigned kGraphFlags = FV_NO_POWER_NORM | FV_NO_L2_NORM | FV_THRESHOLD;
+
+// The model's constants with this call's threshold setting.
+fv::Consts call_consts(const fv_gmm* g, unsigned flags) {
+  fv::Consts c = g->c;
+  c.thresh = (flags & FV_THRESHOLD) ? 1 : 0;
+  return c;
+}
 
 int hip_fail(hipError_t e) {
   t_last_hip_error = (int)e;
@@ -708,7 +717,7 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   if (!gmm || !out || N < 0 || (N > 0 && !X)) return FV_E_INVAL;
   if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
   if (flags & ~kAllFlags) return FV_E_INVAL;
-  const fv::Consts& c = gmm->c;
+  const fv::Consts c = call_consts(gmm, flags);
   if (N > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
   DeviceGuard g(gmm->device);
   if (g.status() != hipSuccess) return hip_fail(g.status());
@@ -786,7 +795,7 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   key.kind = 0;
   key.gmm = gmm;
   key.precision = precision;
-  key.flags = flags & (FV_NO_POWER_NORM | FV_NO_L2_NORM);
+  key.flags = flags & kGraphFlags;
   key.path = (int)path;
   key.P = P;
   key.rows = N;
@@ -814,7 +823,7 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   if (B == 0) return FV_OK;
   const int64_t rows = offsets[B];
   if (rows > 0 && !X) return FV_E_INVAL;
-  const fv::Consts& c = gmm->c;
+  const fv::Consts c = call_consts(gmm, flags);
   if (rows > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
 
   // Frame-relative chunking: frame b's chunk j covers its rows [j*P, (j+1)*P).
@@ -927,7 +936,7 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   key.kind = 1;
   key.gmm = gmm;
   key.precision = precision;
-  key.flags = flags & (FV_NO_POWER_NORM | FV_NO_L2_NORM);
+  key.flags = flags & kGraphFlags;
   key.path = (int)path;
   key.P = P;
   key.rows = rows;

@@ -365,16 +365,48 @@ __device__ __forceinline__ void load_a_lds(float* __restrict__ as, const float* 
   for (int g = 0; g < DP / 4; ++g) *reinterpret_cast<f32x4*>(dst + 4 * g) = src[g * 64];
 }
 
+// ---- the paper's posterior threshold --------------------------------------------------------
+// gamma <= thr contributes nothing (thr < 0: every term contributes).  thr is uniform, so the
+// test is a scalar branch.
+__device__ __forceinline__ void apply_threshold(f32x16& g, float thr) {
+  if (thr >= 0.f) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) g[r] = g[r] > thr ? g[r] : 0.f;
+  }
+}
+
+// True when no lane of the wave has a nonzero value in v (a wave-uniform answer).
+__device__ __forceinline__ bool wave_all_zero(bool nonzero) {
+  return __builtin_amdgcn_ballot_w64(nonzero) == 0;
+}
+
+// Bit s set when gamma register s is nonzero in some lane (all bits set without SKIP).  The
+// mask is taken before the contraction so that its steps stay one straight block each.
+template <bool SKIP>
+__device__ __forceinline__ uint32_t live_steps(const f32x16& gam) {
+  uint32_t live = 0xffffu;
+  if (SKIP) {
+    live = 0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) live |= wave_all_zero(gam[s] != 0.f) ? 0u : (1u << s);
+  }
+  return live;
+}
+
 // ---- statistics on FP32 MFMA -----------------------------------------------------------------
 // acc[b] (rows = features 32b..32b+31 of [x, x^2], cols = the wave's components) +=
 // sum over the tile's rows of Xa[row][f] * gamma[row][comp].  gam is in E-step C layout.
-template <int DP>
+// With SKIP, a step whose gamma is zero in every lane is left out (its MFMAs would add exact
+// zeros for finite descriptors): the paper's early termination, per 2-row step.
+template <int DP, bool SKIP = false>
 __device__ __forceinline__ void stats_f32(const float* __restrict__ xb, int h, int j,
                                           const f32x16& gam, f32x16 (&acc)[2 * DP / 32]) {
   constexpr int XS = 2 * DP + 4;
   constexpr int NB = 2 * DP / 32;
+  const uint32_t live = live_steps<SKIP>(gam);
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
+    if (SKIP && !(live & (1u << s))) continue;
     const float* xrow = xb + crow(s, h) * XS + j;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -384,7 +416,7 @@ __device__ __forceinline__ void stats_f32(const float* __restrict__ xb, int h, i
 
 // Same contraction from an x-only tile (row stride DP + 4): feature f < DP is x[f], feature
 // f >= DP is x[f - DP]^2, squared on the fly.
-template <int DP>
+template <int DP, bool SKIP = false>
 __device__ __forceinline__ void stats_f32_x(const float* __restrict__ xb, int h, int j,
                                             const f32x16& gam, f32x16 (&acc)[2 * DP / 32]) {
   constexpr int XS = DP + 4;
@@ -402,6 +434,7 @@ __device__ __forceinline__ void stats_f32_x(const float* __restrict__ xb, int h,
         v[b] = xrow[f < DP ? f : f - DP];
     }
   };
+  const uint32_t live = live_steps<SKIP>(gam);
   float vn[NB];
   fetch(0, vn);
 #pragma unroll
@@ -410,6 +443,7 @@ __device__ __forceinline__ void stats_f32_x(const float* __restrict__ xb, int h,
 #pragma unroll
     for (int b = 0; b < NB; ++b) v[b] = vn[b];
     if (s + 1 < 16) fetch(s + 1, vn);
+    if (SKIP && !(live & (1u << s))) continue;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int f = 32 * b + j;

@@ -281,13 +281,25 @@ __device__ __forceinline__ void estep16(const Tile16<DP>& t, int j, int h,
 
 // Statistics, 16-bit operands: acc[b] += XT[32b + j][rows] . gamma[rows][comp], gamma split
 // into hi/lo from the E-step result registers (k-step q uses registers 8q..8q+7).
-template <int DP, class T, bool SPLIT>
+// With SKIP, a 16-row step whose gamma is zero in every lane is left out.
+template <int DP, class T, bool SPLIT, bool SKIP = false>
 __device__ __forceinline__ void stats16(const Tile16<DP>& t, int j, int h, const f32x16& gam,
                                         f32x16 (&acc)[2 * DP / 32]) {
   using V = typename P16<T>::v8;
   constexpr int NB = 2 * DP / 32;
+  bool live[2] = {true, true};
+  if (SKIP) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      bool nz = false;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) nz |= gam[8 * q + e] != 0.f;
+      live[q] = !wave_all_zero(nz);
+    }
+  }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
+    if (SKIP && !live[q]) continue;
     V gh, gl;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {

@@ -15,6 +15,9 @@ constexpr int kMaxWaves = 8;      // 8 waves x 32 components = 256 components pe
 constexpr int kFusedMaxK = kCompsPerWave * kMaxWaves;  // fused single-pass kernel
 constexpr int kMaxK = 1024;                               // two-pass path
 constexpr int kMaxD = 96;
+// The paper's posterior threshold (Algorithm 1): with it on, a term enters the statistics only
+// if its posterior exceeds kTau.
+constexpr float kTau = 1e-6f;
 
 // Device-resident constants of one GMM (all pointers are device memory owned by the handle).
 struct Consts {
@@ -42,6 +45,8 @@ struct Consts {
   const double* ivar64;  // 1/sigma^2
   const double* cu64;    // 1/sqrt(w)
   const double* cv64;    // 1/sqrt(2 w)
+  // Per call, not per model: nonzero applies kTau (the API sets it on its own copy)
+  int thresh;
 };
 
 // A chunk of consecutive descriptor rows whose statistics go to one partial slot.

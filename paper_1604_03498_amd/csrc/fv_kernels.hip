@@ -27,7 +27,7 @@ namespace {
 
 using namespace dev;
 
-template <int DP, int W, bool LSE>
+template <int DP, int W, bool LSE, bool TH>
 __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float* __restrict__ A32,
@@ -130,12 +130,13 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
         }
       }
       if (!LSE) {
+        if (TH) apply_threshold(e, kTau);
 #pragma unroll
         for (int r = 0; r < 16; ++r) s0 += e[r];
         if constexpr (ALDS)
-          stats_f32_x<DP>(xb, h, j, e, acc);
+          stats_f32_x<DP, TH>(xb, h, j, e, acc);
         else
-          stats_f32<DP>(xb, h, j, e, acc);
+          stats_f32<DP, TH>(xb, h, j, e, acc);
       }
 
       if (has_next) IO::store(xs[buf ^ 1], pre, tid);
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
 // Second pass over whole component groups (see normext16_kernel): the fused kernel's layout
 // (W waves x 32 components, a shared double-buffered tile), gamma from the first pass's
 // per-row normalisers, one barrier per tile.
-template <int DP, int W>
+template <int DP, int W, bool TH>
 __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float2* __restrict__ lse, int G,
@@ -261,9 +262,10 @@ __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
           gam[r] = fast_exp2(((hi[r] - Ms[p]) + lo[r]) - Ls[p]);
         }
       }
+      if (TH) apply_threshold(gam, kTau);
 #pragma unroll
       for (int r = 0; r < 16; ++r) s0 += gam[r];
-      stats_f32<DP>(xb, h, j, gam, acc);
+      stats_f32<DP, TH>(xb, h, j, gam, acc);
 
       if (has_next) stage(buf ^ 1, t + 1);
       __syncthreads();
@@ -291,9 +293,15 @@ template <int DP, int W>
 hipError_t launch_normext_dp(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
                              const Item* items, int n_items, int grid, const float2* lse,
                              int64_t lse_stride, float* partials, hipStream_t stream) {
-  hipLaunchKernelGGL((normext_f32_kernel<DP, W>), dim3(grid, c.Kp / (kCompsPerWave * W)), dim3(64 * W), 0,
-                     stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c),
-                     lse_stride, c.A32, c.c32, c.Kp, partials);
+  const dim3 grd(grid, c.Kp / (kCompsPerWave * W));
+  if (c.thresh)
+    hipLaunchKernelGGL((normext_f32_kernel<DP, W, true>), grd, dim3(64 * W), 0, stream, X, c.D,
+                       vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c), lse_stride,
+                       c.A32, c.c32, c.Kp, partials);
+  else
+    hipLaunchKernelGGL((normext_f32_kernel<DP, W, false>), grd, dim3(64 * W), 0, stream, X, c.D,
+                       vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c), lse_stride,
+                       c.A32, c.c32, c.Kp, partials);
   return hipGetLastError();
 }
 
@@ -316,9 +324,17 @@ template <int DP, int W, bool LSE>
 hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
                         const Item* items, int n_items, int grid, int groups, float* partials,
                         float2* lse, int64_t lse_stride, hipStream_t stream) {
-  hipLaunchKernelGGL((fused_f32_kernel<DP, W, LSE>), dim3(grid, groups), dim3(64 * W), 0, stream,
-                     X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32, c.Kp, partials,
-                     lse, lse_stride);
+  if constexpr (!LSE) {
+    if (c.thresh) {
+      hipLaunchKernelGGL((fused_f32_kernel<DP, W, false, true>), dim3(grid, groups), dim3(64 * W),
+                         0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32,
+                         c.Kp, partials, lse, lse_stride);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((fused_f32_kernel<DP, W, LSE, false>), dim3(grid, groups), dim3(64 * W), 0,
+                     stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32, c.Kp,
+                     partials, lse, lse_stride);
   return hipGetLastError();
 }
 

@@ -208,7 +208,7 @@ int launch(fv_server* s, Lane& L) {
       return FV_E_DEVICE;
   }
   const unsigned fl = FV_X_DEVICE | FV_OUT_DEVICE | FV_ASYNC |
-                      (s->cfg.flags & (FV_NO_POWER_NORM | FV_NO_L2_NORM));
+                      (s->cfg.flags & (FV_NO_POWER_NORM | FV_NO_L2_NORM | FV_THRESHOLD));
   int rc = fv_encode_batch(s->gmm, L.dX, off.data(), B, L.dOut, s->cfg.precision, fl, L.stream);
   if (rc != FV_OK) return rc;
   for (int b = 0; b < B; ++b)
@@ -368,7 +368,7 @@ int fv_server_create(const fv_gmm* gmm, const fv_server_config* cfg, fv_server**
   fv_server_config c = *cfg;
   if (c.executor != FV_EXEC_HIP && c.executor != FV_EXEC_FAKE) return FV_E_INVAL;
   if (c.precision < FV_PREC_FP32 || c.precision > FV_PREC_BF16) return FV_E_INVAL;
-  if (c.flags & ~(FV_NO_POWER_NORM | FV_NO_L2_NORM)) return FV_E_INVAL;
+  if (c.flags & ~(FV_NO_POWER_NORM | FV_NO_L2_NORM | FV_THRESHOLD)) return FV_E_INVAL;
   if (c.executor == FV_EXEC_HIP && !gmm) return FV_E_INVAL;
   if (!gmm && (c.fake_K < 1 || c.fake_D < 1)) return FV_E_INVAL;
   if (c.max_queue <= 0) c.max_queue = 4096;

@@ -25,7 +25,7 @@ using namespace dev;
 
 constexpr int kSliceWaves = 4;
 
-template <int DP>
+template <int DP, bool TH>
 __global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float2* __restrict__ lse, int G,
@@ -115,9 +115,10 @@ __global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
           gam[r] = fast_exp2(((hi[r] - Ms[p]) + lo[r]) - Ls[p]);
         }
       }
+      if (TH) apply_threshold(gam, kTau);
 #pragma unroll
       for (int r = 0; r < 16; ++r) s0 += gam[r];
-      stats_f32<DP>(xw, h, j, gam, acc);
+      stats_f32<DP, TH>(xw, h, j, gam, acc);
       wave_sync();
     }
 
@@ -157,9 +158,14 @@ hipError_t launch_sliced_dp(const Consts& c, const float* X, bool vec_ok, int64_
                             const Item* items, int n_items, int grid, const float2* lse,
                             int64_t lse_stride, float* partials, hipStream_t stream) {
   const int slices = c.Kp / kCompsPerWave;
-  hipLaunchKernelGGL((sliced_f32_kernel<DP>), dim3(grid, slices), dim3(64 * kSliceWaves), 0,
-                     stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c),
-                     lse_stride, c.A32, c.c32, c.Kp, partials);
+  if (c.thresh)
+    hipLaunchKernelGGL((sliced_f32_kernel<DP, true>), dim3(grid, slices), dim3(64 * kSliceWaves),
+                       0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse,
+                       lse_groups(c), lse_stride, c.A32, c.c32, c.Kp, partials);
+  else
+    hipLaunchKernelGGL((sliced_f32_kernel<DP, false>), dim3(grid, slices), dim3(64 * kSliceWaves),
+                       0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse,
+                       lse_groups(c), lse_stride, c.A32, c.c32, c.Kp, partials);
   return hipGetLastError();
 }
 

@@ -15,7 +15,8 @@ OK, PENDING = 0, 1
 E_INVAL, E_NOMEM, E_DEVICE, E_BUDGET = -1, -2, -3, -4
 E_AGAIN, E_NOTFOUND, E_TIMEOUT, E_UNSUPPORTED = -5, -6, -7, -8
 PREC_FP32, PREC_BF16_SPLIT, PREC_FP16_SPLIT, PREC_BF16 = 0, 1, 2, 3
-X_DEVICE, OUT_DEVICE, NO_POWER_NORM, NO_L2_NORM, ASYNC = 1, 2, 4, 8, 16
+X_DEVICE, OUT_DEVICE, NO_POWER_NORM, NO_L2_NORM, ASYNC, THRESHOLD = 1, 2, 4, 8, 16, 32
+THRESHOLD_TAU = 1e-6  # posteriors at or below it are left out under THRESHOLD
 
 EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "fv_encode",
                     "fv_encode_batch", "fv_gmm_set_tuning", "fv_gmm_get_tuning",

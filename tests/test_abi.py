@@ -26,6 +26,16 @@ def test_exports_every_declared_symbol():
         assert hasattr(lib, s), s
 
 
+def test_binding_constants_match_header():
+    """Every FV_* #define of the header has the same value in the Python binding."""
+    txt = open(os.path.join(ROOT, "include", "fv.h")).read()
+    defs = dict(re.findall(r"#define FV_([A-Z0-9_]+) \(?(-?[0-9.e+-]+)u?\)?", txt))
+    assert len(defs) > 20
+    for name, val in defs.items():
+        assert hasattr(fv, name), name
+        assert float(getattr(fv, name)) == float(val), name
+
+
 def test_strerror_and_limits():
     assert fv.strerror(fv.OK) == "ok"
     assert fv.strerror(fv.E_INVAL) == "invalid argument"

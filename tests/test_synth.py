@@ -27,6 +27,10 @@ def test_frame_recipe():
     assert X.shape == (8000, 64) and X.dtype == np.float32
     # exactly round(0.05 N) rows are uniform outliers in [-4, 4]; they are bounded
     assert np.abs(X).max() < 20
+    # the clustered frame holds the same rows, reordered so that labels do not decrease
+    Xc = fvsynth.frame(g, 8000, 100, 0.05, clustered=True)
+    assert np.array_equal(np.sort(Xc.view(np.uint32), axis=None), np.sort(X.view(np.uint32), axis=None))
+    assert not np.array_equal(Xc, X)
     sizes = fvsynth.batch_sizes(64, 1)
     assert sizes.min() >= 2000 and sizes.max() <= 20000 and len(sizes) == 64
 
