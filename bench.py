@@ -158,6 +158,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch with the default tuning instead of the measuring autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-projection", action="store_true",
+                    help="skip the projection-prologue measurements")
     ap.add_argument("--no-paper-mode", action="store_true",
                     help="skip the posterior-threshold (paper mode) measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -516,6 +518,67 @@ def main():
         if batch:
             fv.set_tuning(hb)
 
+    # Projection prologue (raw 130-value descriptors -> D = 64 by y = A (x - m), then the
+    # encode), on the same frame and batch drawn through the stand-in PCA
+    projected = {}
+    if not a.no_projection and not a.no_frame:
+        pc = fvsynth.pca(D, 0)
+        hp = fv.pca_load(pc.A, pc.mean)
+        w2 = fvsynth.WORKLOADS["c2_frame_k256_d64_n8000"]
+        Xr = fvsynth.raw_frame(g, pc, N, w2["frame_seed"], w2["outliers"])
+        Xrd = torch.from_numpy(Xr).to(dev)
+        runs = [("frame", Xrd, None)]
+        if batch:
+            w4 = fvsynth.WORKLOADS["c4_batch64_k256_d64"]
+            Xrb, offrb = fvsynth.raw_batch(g, pc, fvsynth.batch_sizes(w4["B"], w4["sizes_seed"]),
+                                           w4["frame_seed0"], w4["outliers"])
+            runs.append(("batch", torch.from_numpy(Xrb).to(dev), offrb))
+        for form in forms:
+            projected[form] = {}
+            for name, xin, offr in runs:
+                nrows = int(xin.shape[0])
+                shape = (2 * K * D,) if offr is None else (offr.size - 1, 2 * K * D)
+                out = torch.empty(shape, dtype=torch.float32, device=dev)
+                prec = PREC_CODE[form]
+                if offr is not None and form in batch:
+                    fv.set_tuning(hb, batch_path=1 if batch[form]["tuned"]["path"] == "fused" else 2,
+                                  batch_chunk=batch[form]["tuned"]["chunk"])
+
+                def pstep():
+                    if offr is None:
+                        fv.encode_projected(h, hp, xin, out=out, precision=prec, flags=fv.ASYNC,
+                                            stream=stream)
+                    else:
+                        fv.encode_batch_projected(h, hp, xin, offr, out=out, precision=prec,
+                                                  flags=fv.ASYNC, stream=stream)
+                steps = a.steps if offr is None else a.batch_steps
+                for _ in range(a.warmup if offr is None else 2):
+                    pstep()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    pstep()
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                fv.kernel_timing(True)
+                for _ in range(max(5, min(steps, 50))):
+                    pstep()
+                torch.cuda.synchronize()
+                pr_ms, pr_n = fv.kernel_timing_read(2)
+                fv.kernel_timing(False)
+                pr_avg = pr_ms / max(pr_n, 1)
+                # projection algorithmic bytes: read Din, write D floats per descriptor
+                pbytes = nrows * 4.0 * (Xr.shape[1] + D)
+                projected[form][name] = {
+                    "value": nrows * steps / el, "ms_per_step": el * 1e3 / steps,
+                    "projection_avg_us": round(pr_avg * 1e3, 3),
+                    "projection_gbps": round(pbytes / (pr_avg * 1e-3) / 1e9, 1) if pr_avg > 0 else None}
+                log(f"[bench] projected {name} form={form}: {nrows * steps / el:.4e} desc/s, "
+                    f"projection {pr_avg * 1e3:.2f} us")
+        if batch:
+            fv.set_tuning(hb)
+        hp.free()
+
     serving = []
     if a.serving_seconds > 0:
         for budget in (2 << 30, 64 << 20):
@@ -576,6 +639,11 @@ def main():
         result["serving_sweep"] = sweep
     if c5:
         result["c5_capacity_device_input"] = c5
+    if projected:
+        result["projected_din130"] = {
+            "forms": projected,
+            "note": "raw 130-value descriptors (128 stand-in SIFT + 2 coordinates) projected to "
+                    "D = 64 by y = A (x - m) on the GPU, then encoded; the same GMM and frames"}
     if paper:
         result["paper_threshold_mode"] = {
             "tau": fv.THRESHOLD_TAU, "forms": paper,

@@ -9,6 +9,15 @@
   clustered=True the rows are then stably reordered by label (a frame whose neighbouring
   descriptors come from the same component, as neighbouring patches of one region do).
 * batch_sizes(B, seed=1, lo=2000, hi=20000): default_rng(seed).integers(lo, hi+1, B).
+* pca(D, seed, n_sift=128): a stand-in for a trained PCA of 128-D SIFT descriptors reduced to
+  m = D - 2 dimensions plus two appended coordinates.  rng = default_rng(seed);
+  Q = orthonormal [n_sift x m] (QR of N(0,1)^{n_sift x m}, signs fixed so diag(R) > 0);
+  sift_mean ~ U[0, 0.2]^{n_sift}.  A = [[Q^T, 0], [0, I_2]] ([D x (n_sift + 2)]) and
+  mean = [sift_mean, 0, 0], cast to float32.
+* raw_frame(g, p, N, seed, outlier_frac, noise=0.05): y = frame(g, N, seed, outlier_frac) in
+  D dimensions; n ~ N(0, noise^2)^{N x n_sift} from default_rng(seed + 1_000_003);
+  sift = sift_mean + y[:, :m] Q^T + n (I - Q Q^T); raw = [sift, y[:, m:]], cast to float32.
+  So A (raw - mean) = y up to the float32 rounding of raw.
 * serving_plan(...): 16 streams, Poisson arrivals at a rate per stream, resolutions
   assigned round-robin from 320x240 .. 640x480, N = 8000 * area / (320*240).
 """
@@ -61,6 +70,54 @@ def frame(g: Gmm, N: int, seed: int, outlier_frac: float = 0.0,
     if clustered:
         x = x[np.argsort(labels, kind="stable")]
     return np.ascontiguousarray(x.astype(np.float32))
+
+
+@dataclass(frozen=True)
+class Pca:
+    A: np.ndarray      # [D, Din] float32
+    mean: np.ndarray   # [Din] float32
+    Q: np.ndarray      # [n_sift, m] float64 (generation only)
+
+    @property
+    def Din(self) -> int:
+        return int(self.A.shape[1])
+
+    @property
+    def D(self) -> int:
+        return int(self.A.shape[0])
+
+
+def pca(D: int, seed: int = 0, n_sift: int = 128) -> Pca:
+    m = D - 2
+    rng = np.random.default_rng(seed)
+    q, r = np.linalg.qr(rng.standard_normal((n_sift, m)))
+    q = q * np.sign(np.diag(r))[None, :]
+    sift_mean = rng.uniform(0.0, 0.2, n_sift)
+    A = np.zeros((D, n_sift + 2))
+    A[:m, :n_sift] = q.T
+    A[m, n_sift] = 1.0
+    A[m + 1, n_sift + 1] = 1.0
+    mean = np.concatenate([sift_mean, [0.0, 0.0]])
+    return Pca(A=A.astype(np.float32), mean=mean.astype(np.float32), Q=q)
+
+
+def raw_frame(g: Gmm, p: Pca, N: int, seed: int, outlier_frac: float = 0.0,
+              noise: float = 0.05) -> np.ndarray:
+    y = frame(g, N, seed, outlier_frac).astype(np.float64)
+    q = p.Q
+    m = q.shape[1]
+    n = np.random.default_rng(seed + 1_000_003).standard_normal((N, q.shape[0])) * noise
+    perp = n - (n @ q) @ q.T
+    sift = p.mean[:q.shape[0]].astype(np.float64) + y[:, :m] @ q.T + perp
+    return np.ascontiguousarray(np.concatenate([sift, y[:, m:]], axis=1).astype(np.float32))
+
+
+def raw_batch(g: Gmm, p: Pca, sizes, seed0: int = 200, outlier_frac: float = 0.05):
+    frames = [raw_frame(g, p, int(n), seed0 + f, outlier_frac) for f, n in enumerate(sizes)]
+    offsets = np.zeros(len(frames) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([f.shape[0] for f in frames])
+    X = np.concatenate(frames, axis=0) if frames else np.zeros((0, p.Din), np.float32)
+    return np.ascontiguousarray(X), offsets
 
 
 def batch_sizes(B: int, seed: int = 1, lo: int = 2000, hi: int = 20000) -> np.ndarray:

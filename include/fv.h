@@ -144,11 +144,52 @@ int fv_gmm_get_tuning(const fv_gmm* gmm, fv_tuning* tuning);
  * the counters and starts bracketing every launch of libfv's kernels with HIP events on the
  * stream the kernel is launched on; fv_kernel_timing(0) stops.  fv_kernel_timing_read waits
  * for the recorded events and returns the summed device duration (ms) and the launch count
- * of kernel class `which` (0 = statistics kernel, 1 = finalize kernels) since the reset.
+ * of kernel class `which` (0 = statistics kernels, 1 = finalize kernels, 2 = projection
+ * kernel) since the reset.
  * Errors: FV_E_INVAL (bad `which`), FV_E_DEVICE.
  */
 int fv_kernel_timing(int enable);
 int fv_kernel_timing_read(int which, double* total_ms, int64_t* launches);
+
+/* ---- projection prologue ------------------------------------------------------------- */
+/*
+ * Dimension reduction of the raw descriptors before encoding (Sec. 3.1: the 128 dense-SIFT
+ * values are reduced to m dimensions by PCA and the normalised image coordinates appended,
+ * giving the D = m + 2 the GMM is trained on).  The prologue computes, per descriptor,
+ *   y = A (x - m),   A [D x Din] row-major, m [Din]
+ * so appended coordinates are identity rows of A (with m = 0 in their columns).  One FP32
+ * MFMA contraction per 32-descriptor tile; y is FP32 in every precision form.
+ *
+ * fv_pca_load copies A and m (host pointers) to `device` and precomputes -A m in FP64.
+ * Requires 1 <= Din <= 256 (FV_E_UNSUPPORTED above), 1 <= D <= the fv_limits maximum, and
+ * finite values, else FV_E_INVAL.  The handle is immutable and may be shared across threads;
+ * fv_pca_free releases it.
+ */
+typedef struct fv_pca fv_pca;
+int fv_pca_load(int Din, int D, const float* A, const float* mean, int device, fv_pca** out);
+int fv_pca_free(fv_pca* pca);
+int fv_pca_info(const fv_pca* pca, int* Din, int* D, int* device);
+
+/*
+ * Projection alone: X [N x Din] -> Y [N x D], both row-major float32; FV_X_DEVICE and
+ * FV_OUT_DEVICE say where X and Y live, FV_ASYNC as for fv_encode.  Errors: FV_E_INVAL
+ * (null pointers, N < 0, other flags), FV_E_NOMEM, FV_E_DEVICE.
+ */
+int fv_project(const fv_pca* pca, const float* X, int64_t N, float* Y, unsigned flags,
+               void* hip_stream);
+
+/*
+ * fv_encode / fv_encode_batch of the projected descriptors: X holds raw descriptors of Din
+ * values per row (host or device, per FV_X_DEVICE); the projection runs on the device into
+ * the library's scratch and feeds the encoder, within the same stream order (and the same
+ * captured graph).  Requires pca's D == gmm's D and the same device, else FV_E_INVAL.
+ * Otherwise as fv_encode / fv_encode_batch.
+ */
+int fv_encode_projected(const fv_gmm* gmm, const fv_pca* pca, const float* X, int64_t N,
+                        float* out, int precision, unsigned flags, void* hip_stream);
+int fv_encode_batch_projected(const fv_gmm* gmm, const fv_pca* pca, const float* X,
+                              const int64_t* offsets, int B, float* out, int precision,
+                              unsigned flags, void* hip_stream);
 
 /* ---- serving ------------------------------------------------------------------------------
  * A server keeps one GMM and its own HIP streams, accepts frames of any size from any thread,

@@ -44,6 +44,8 @@ class OracleLib:
         p = ctypes.c_void_p
         lib.fvo_posteriors.argtypes = [i64, i32, i32, p, p, p, p, p]
         lib.fvo_encode_tau.argtypes = [i64, i32, i32, p, p, p, p, u32, f64, p]
+        lib.fvo_encode_tau_f64.argtypes = [i64, i32, i32, p, p, p, p, u32, f64, p]
+        lib.fvo_encode_tau_f64.restype = ctypes.c_int
         lib.fvo_encode.argtypes = [i64, i32, i32, p, p, p, p, u32, p]
         lib.fvo_encode_batch.argtypes = [i32, p, i32, i32, p, p, p, p, u32, i32, p]
         lib.fvo_max_threads.argtypes = []
@@ -74,6 +76,19 @@ class OracleLib:
         t = -1.0 if tau is None else float(tau)
         rc = self.lib.fvo_encode_tau(X.shape[0], K, D, _ptr(X), _ptr(w), _ptr(mu), _ptr(var),
                                      int(flags), t, _ptr(out))
+        if rc:
+            raise RuntimeError("oracle encode failed")
+        return out
+
+    def encode_f64(self, X, weights, means, variances, flags: int = 0,
+                   tau: float | None = None) -> np.ndarray:
+        """As encode, for float64 descriptors (used as given, no rounding to float32)."""
+        w, mu, var, K, D = _model(weights, means, variances)
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, D)
+        out = np.empty(2 * K * D, dtype=np.float64)
+        t = -1.0 if tau is None else float(tau)
+        rc = self.lib.fvo_encode_tau_f64(X.shape[0], K, D, _ptr(X), _ptr(w), _ptr(mu), _ptr(var),
+                                         int(flags), t, _ptr(out))
         if rc:
             raise RuntimeError("oracle encode failed")
         return out
@@ -158,3 +173,18 @@ def max_threads() -> int:
 
 def encode_gmm(X, g, flags: int = 0, tau: float | None = None) -> np.ndarray:
     return encode(X, g.weights, g.means, g.variances, flags, tau)
+
+
+def project(X, A, mean) -> np.ndarray:
+    """The projection prologue y = A (x - m) in float64 (Sec. 3.1: PCA of the SIFT values plus
+    the appended coordinates, written as one affine map): X [N, Din], A [D, Din], mean [Din],
+    all promoted exactly from float32; one library matrix product."""
+    X64 = np.asarray(X, dtype=np.float32).astype(np.float64)
+    A64 = np.asarray(A, dtype=np.float32).astype(np.float64)
+    m64 = np.asarray(mean, dtype=np.float32).astype(np.float64)
+    return (X64 - m64) @ A64.T
+
+
+def encode_projected(X, A, mean, g, flags: int = 0, tau: float | None = None) -> np.ndarray:
+    """Fisher vector of the projected descriptors, the projection kept in float64."""
+    return _load().encode_f64(project(X, A, mean), g.weights, g.means, g.variances, flags, tau)

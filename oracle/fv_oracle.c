@@ -24,7 +24,8 @@
  *   8. unless FVO_NO_POWER: phi_i <- sign(phi_i) sqrt(|phi_i|)
  *   9. unless FVO_NO_L2:    phi <- phi / ||phi||_2  (left as is when the norm is 0)
  * Everything is evaluated in IEEE double, sums run sequentially in index order.  Inputs are
- * the float32 arrays the GPU receives, promoted exactly to double.  Weights are used as given.
+ * the float32 arrays the GPU receives, promoted exactly to double, or (the _f64 entry points)
+ * double descriptors, such as the exact output of a projection.  Weights are used as given.
  */
 #include <math.h>
 #include <stdint.h>
@@ -37,9 +38,17 @@
 #define FVO_NO_POWER 1u
 #define FVO_NO_L2 2u
 
+/* Exact promotion of float32 descriptors to double (NULL on OOM). */
+static double* promote(int64_t N, int D, const float* X) {
+  double* Xd = (double*)malloc(sizeof(double) * ((size_t)N * D + 1));
+  if (!Xd) return NULL;
+  for (size_t i = 0; i < (size_t)N * D; ++i) Xd[i] = (double)X[i];
+  return Xd;
+}
+
 /* Steps 1-4 for one frame: gamma [N x K], row-major.  Returns 0, or -1 on bad sizes / OOM. */
-int fvo_posteriors(int64_t N, int K, int D, const float* X, const float* w, const float* mu,
-                   const float* var, double* gamma) {
+int fvo_posteriors_f64(int64_t N, int K, int D, const double* X, const float* w, const float* mu,
+                       const float* var, double* gamma) {
   if (N < 0 || K < 1 || D < 1) return -1;
   double* s = (double*)malloc(sizeof(double) * (size_t)K * D);
   double* logdet_half = (double*)malloc(sizeof(double) * K);
@@ -54,7 +63,7 @@ int fvo_posteriors(int64_t N, int K, int D, const float* X, const float* w, cons
     logdet_half[k] = 0.5 * acc;
   }
   for (int64_t t = 0; t < N; ++t) {
-    const float* x = X + (size_t)t * D;
+    const double* x = X + (size_t)t * D;
     double* g = gamma + (size_t)t * K;
     double m = -INFINITY;
     for (int k = 0; k < K; ++k) {
@@ -79,9 +88,19 @@ int fvo_posteriors(int64_t N, int K, int D, const float* X, const float* w, cons
   return 0;
 }
 
+int fvo_posteriors(int64_t N, int K, int D, const float* X, const float* w, const float* mu,
+                   const float* var, double* gamma) {
+  if (N < 0 || K < 1 || D < 1) return -1;
+  double* Xd = promote(N, D, X);
+  if (!Xd) return -1;
+  int rc = fvo_posteriors_f64(N, K, D, Xd, w, mu, var, gamma);
+  free(Xd);
+  return rc;
+}
+
 /* Steps 1-9 for one frame.  out has 2KD doubles.  tau < 0 disables the threshold. */
-int fvo_encode_tau(int64_t N, int K, int D, const float* X, const float* w, const float* mu,
-                   const float* var, unsigned flags, double tau, double* out) {
+int fvo_encode_tau_f64(int64_t N, int K, int D, const double* X, const float* w, const float* mu,
+                       const float* var, unsigned flags, double tau, double* out) {
   if (N < 0 || K < 1 || D < 1) return -1;
   const size_t KD = (size_t)K * D;
   memset(out, 0, sizeof(double) * 2 * KD);
@@ -89,12 +108,12 @@ int fvo_encode_tau(int64_t N, int K, int D, const float* X, const float* w, cons
   double* gamma = (double*)malloc(sizeof(double) * (size_t)N * K);
   double* s = (double*)malloc(sizeof(double) * KD);
   if (!gamma || !s) { free(gamma); free(s); return -1; }
-  if (fvo_posteriors(N, K, D, X, w, mu, var, gamma) != 0) { free(gamma); free(s); return -1; }
+  if (fvo_posteriors_f64(N, K, D, X, w, mu, var, gamma) != 0) { free(gamma); free(s); return -1; }
   for (size_t i = 0; i < KD; ++i) s[i] = 1.0 / sqrt((double)var[i]);
   double* U = out;
   double* V = out + KD;
   for (int64_t t = 0; t < N; ++t) {
-    const float* x = X + (size_t)t * D;
+    const double* x = X + (size_t)t * D;
     for (int k = 0; k < K; ++k) {
       double g = gamma[(size_t)t * K + k];
       if (tau >= 0.0 && !(g > tau)) continue;
@@ -130,6 +149,16 @@ int fvo_encode_tau(int64_t N, int K, int D, const float* X, const float* w, cons
   free(gamma);
   free(s);
   return 0;
+}
+
+int fvo_encode_tau(int64_t N, int K, int D, const float* X, const float* w, const float* mu,
+                   const float* var, unsigned flags, double tau, double* out) {
+  if (N < 0 || K < 1 || D < 1) return -1;
+  double* Xd = promote(N, D, X);
+  if (!Xd) return -1;
+  int rc = fvo_encode_tau_f64(N, K, D, Xd, w, mu, var, flags, tau, out);
+  free(Xd);
+  return rc;
 }
 
 int fvo_encode(int64_t N, int K, int D, const float* X, const float* w, const float* mu,

@@ -11,5 +11,6 @@ from .fv import (  # noqa: F401
     E_UNSUPPORTED, PREC_FP32, PREC_BF16_SPLIT, PREC_FP16_SPLIT, PREC_BF16, X_DEVICE, OUT_DEVICE,
     NO_POWER_NORM, NO_L2_NORM, ASYNC, THRESHOLD, THRESHOLD_TAU, EXPORTED_SYMBOLS, EXEC_HIP,
     EXEC_FAKE, Server, ServerConfig,
-    server_config, set_tuning, get_tuning, Tuning,
+    server_config, set_tuning, get_tuning, Tuning, Pca, pca_load, project, encode_projected,
+    encode_batch_projected,
 )

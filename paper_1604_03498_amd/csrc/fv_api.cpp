@@ -93,10 +93,12 @@ struct GraphKey {
   const void* out = nullptr;
   const void* dev = nullptr;
   const void* pinned = nullptr;
+  const fv_pca* pca = nullptr;
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && gmm == o.gmm && precision == o.precision && flags == o.flags &&
            path == o.path && P == o.P && rows == o.rows && B == o.B && n_items == o.n_items &&
-           n_groups == o.n_groups && X == o.X && out == o.out && dev == o.dev && pinned == o.pinned;
+           n_groups == o.n_groups && X == o.X && out == o.out && dev == o.dev &&
+           pinned == o.pinned && pca == o.pca;
   }
 };
 
@@ -391,10 +393,10 @@ int batch_chunk(const fv_gmm* g) {
 struct TimingState {
   std::mutex mu;
   bool enabled = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
   std::vector<hipEvent_t> pool;
-  double total_ms[2] = {0.0, 0.0};
-  int64_t launches[2] = {0, 0};
+  double total_ms[3] = {0.0, 0.0, 0.0};
+  int64_t launches[3] = {0, 0, 0};
 };
 TimingState g_timing;
 
@@ -438,6 +440,13 @@ void timing_end(hipEvent_t start, int which, hipStream_t s) {
   g_timing.pending[which].push_back({start, e});
 }
 
+// Workgroups of the projection kernel: two per CU (register bound), grid-stride over tiles of
+// at least 32 rows (extra workgroups exit at once).
+int project_grid(int device, int64_t N) {
+  const int64_t tiles = (N + fv::kTile - 1) / fv::kTile;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)device_cu_count(device) * 2));
+}
+
 }  // namespace
 
 namespace fv {
@@ -467,7 +476,7 @@ extern "C" {
 
 int fv_kernel_timing(int enable) {
   std::lock_guard<std::mutex> lk(g_timing.mu);
-  for (int w = 0; w < 2; ++w) {
+  for (int w = 0; w < 3; ++w) {
     for (auto& pr : g_timing.pending[w]) {
       (void)hipEventSynchronize(pr.second);
       g_timing.pool.push_back(pr.first);
@@ -482,7 +491,7 @@ int fv_kernel_timing(int enable) {
 }
 
 int fv_kernel_timing_read(int which, double* total_ms, int64_t* launches) {
-  if (which < 0 || which > 1) return FV_E_INVAL;
+  if (which < 0 || which > 2) return FV_E_INVAL;
   std::lock_guard<std::mutex> lk(g_timing.mu);
   for (auto& pr : g_timing.pending[which]) {
     hipError_t e = hipEventSynchronize(pr.second);
@@ -712,13 +721,16 @@ int fv_gmm_info(const fv_gmm* gmm, int* K, int* D, int* device) {
   return FV_OK;
 }
 
-int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int precision,
-              unsigned flags, void* hip_stream) {
+// fv_encode, with the projection prologue when pca is non-null (X then has pca->Din columns).
+static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int64_t N,
+                       float* out, int precision, unsigned flags, void* hip_stream) {
   if (!gmm || !out || N < 0 || (N > 0 && !X)) return FV_E_INVAL;
   if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
   if (flags & ~kAllFlags) return FV_E_INVAL;
+  if (pca && (pca->D != gmm->D || pca->device != gmm->device)) return FV_E_INVAL;
   const fv::Consts c = call_consts(gmm, flags);
-  if (N > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
+  const int Din = pca ? pca->Din : c.D;
+  if (N > ((int64_t)1 << 40) / std::max(Din, c.D)) return FV_E_UNSUPPORTED;
   DeviceGuard g(gmm->device);
   if (g.status() != hipSuccess) return hip_fail(g.status());
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
@@ -745,9 +757,10 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
   const size_t b_norm = align256((size_t)nblk * 8);
   const size_t b_lse = (path == Path::kSplit) ? align256((size_t)G * N * 8) : 0;
-  const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)N * c.D * 4);
+  const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)N * Din * 4);
   const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256(out_len * 4);
-  int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_x + b_out, s);
+  const size_t b_y = pca ? align256((size_t)N * c.D * 4) : 0;
+  int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_x + b_out + b_y, s);
   if (rc) return rc;
   char* base = ws->dev;
   float* partials = reinterpret_cast<float*>(base);
@@ -755,30 +768,38 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   float2* lse = reinterpret_cast<float2*>(base + b_part + b_norm);
   float* xdev = reinterpret_cast<float*>(base + b_part + b_norm + b_lse);
   float* odev = reinterpret_cast<float*>(base + b_part + b_norm + b_lse + b_x);
+  float* ydev = reinterpret_cast<float*>(base + b_part + b_norm + b_lse + b_x + b_out);
 
   const float* Xd = X;
   if (!(flags & FV_X_DEVICE) && N > 0) {
-    FV_HIP(hipMemcpyAsync(xdev, X, (size_t)N * c.D * 4, hipMemcpyHostToDevice, s));
+    FV_HIP(hipMemcpyAsync(xdev, X, (size_t)N * Din * 4, hipMemcpyHostToDevice, s));
     Xd = xdev;
   }
   if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
   float* Od = (flags & FV_OUT_DEVICE) ? out : odev;
-  const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
+  // the encoder's input: the projected rows (library scratch) or X itself
+  const float* Fx = pca ? ydev : Xd;
+  const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Fx) & 15) == 0);
 
   auto enqueue = [&]() -> int {
+    if (pca && N > 0) {
+      hipEvent_t tp = timing_begin(s);
+      FV_HIP(fv::launch_project(pca->p, Xd, N, ydev, project_grid(gmm->device, N), s));
+      timing_end(tp, 2, s);
+    }
     if (n_items > 0) {
       hipEvent_t t0 = timing_begin(s);
       if (path == Path::kFused) {
-        FV_HIP(run_stats(c, precision, Xd, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
+        FV_HIP(run_stats(c, precision, Fx, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
       } else {
         const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
         const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
-        FV_HIP(run_lse(c, precision, Xd, vec_ok, N, n_tiles, grid1, lse, N, s));
+        FV_HIP(run_lse(c, precision, Fx, vec_ok, N, n_tiles, grid1, lse, N, s));
         if (grouped)
-          FV_HIP(run_normext(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse,
+          FV_HIP(run_normext(c, precision, Fx, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse,
                              N, partials, s));
         else
-          FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
+          FV_HIP(run_sliced(c, precision, Fx, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
                             partials, s));
       }
       timing_end(t0, 0, s);
@@ -804,6 +825,7 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   key.X = Xd;
   key.out = Od;
   key.dev = ws->dev;
+  key.pca = pca;
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   if (!(flags & FV_OUT_DEVICE))
@@ -812,11 +834,14 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
   return FV_OK;
 }
 
-int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, int B, float* out,
-                    int precision, unsigned flags, void* hip_stream) {
+// fv_encode_batch, with the projection prologue when pca is non-null.
+static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X,
+                             const int64_t* offsets, int B, float* out, int precision,
+                             unsigned flags, void* hip_stream) {
   if (!gmm || !offsets || B < 0 || (B > 0 && !out)) return FV_E_INVAL;
   if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
   if (flags & ~kAllFlags) return FV_E_INVAL;
+  if (pca && (pca->D != gmm->D || pca->device != gmm->device)) return FV_E_INVAL;
   if (offsets[0] != 0) return FV_E_INVAL;
   for (int b = 0; b < B; ++b)
     if (offsets[b + 1] < offsets[b]) return FV_E_INVAL;
@@ -824,7 +849,8 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   const int64_t rows = offsets[B];
   if (rows > 0 && !X) return FV_E_INVAL;
   const fv::Consts c = call_consts(gmm, flags);
-  if (rows > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
+  const int Din = pca ? pca->Din : c.D;
+  if (rows > ((int64_t)1 << 40) / std::max(Din, c.D)) return FV_E_UNSUPPORTED;
 
   // Frame-relative chunking: frame b's chunk j covers its rows [j*P, (j+1)*P).
   const Path path = choose_batch(gmm);
@@ -860,9 +886,10 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   const size_t b_items = align256((size_t)n_items * sizeof(fv::Item));
   const size_t b_groups = align256((size_t)n_groups * sizeof(fv::Group));
   const size_t b_tab = b_frames + b_items + b_groups;
-  const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)rows * c.D * 4);
+  const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)rows * Din * 4);
   const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256((size_t)B * out_len * 4);
-  int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_tab + b_x + b_out, s);
+  const size_t b_y = pca ? align256((size_t)rows * c.D * 4) : 0;
+  int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_tab + b_x + b_out + b_y, s);
   if (rc) return rc;
   rc = ensure_pinned(ws, b_tab);
   if (rc) return rc;
@@ -876,6 +903,7 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   fv::Group* dgroups = reinterpret_cast<fv::Group*>(tab + b_frames + b_items);
   float* xdev = reinterpret_cast<float*>(tab + b_tab);
   float* odev = reinterpret_cast<float*>(tab + b_tab + b_x);
+  float* ydev = reinterpret_cast<float*>(tab + b_tab + b_x + b_out);
 
   // work tables in pinned memory (same layout as on the device), then one H2D copy
   fv::Frame* hframes = reinterpret_cast<fv::Frame*>(ws->pinned);
@@ -899,28 +927,34 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   }
   const float* Xd = X;
   if (!(flags & FV_X_DEVICE) && rows > 0) {
-    FV_HIP(hipMemcpyAsync(xdev, X, (size_t)rows * c.D * 4, hipMemcpyHostToDevice, s));
+    FV_HIP(hipMemcpyAsync(xdev, X, (size_t)rows * Din * 4, hipMemcpyHostToDevice, s));
     Xd = xdev;
   }
   if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
   float* Od = (flags & FV_OUT_DEVICE) ? out : odev;
-  const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
+  const float* Fx = pca ? ydev : Xd;  // the encoder's input
+  const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Fx) & 15) == 0);
   // One persistent statistics launch over the work table (grid = resident workgroups), then
   // the finalize; the table copy from pinned memory is part of the sequence.
   auto enqueue = [&]() -> int {
     FV_HIP(hipMemcpyAsync(dframes, ws->pinned, b_tab, hipMemcpyHostToDevice, s));
+    if (pca && rows > 0) {
+      hipEvent_t tp = timing_begin(s);
+      FV_HIP(fv::launch_project(pca->p, Xd, rows, ydev, project_grid(gmm->device, rows), s));
+      timing_end(tp, 2, s);
+    }
     if (n_items > 0) {
       hipEvent_t t0 = timing_begin(s);
       if (path == Path::kFused) {
         const int grid = std::max(1, std::min(n_items, resident_fused(gmm->device, c.Wg)));
-        FV_HIP(run_stats(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid, partials, s));
+        FV_HIP(run_stats(c, precision, Fx, vec_ok, rows, P, ditems, n_items, grid, partials, s));
       } else {
         const int n_tiles = (int)((rows + fv::kTile - 1) / fv::kTile);
         const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
-        FV_HIP(run_lse(c, precision, Xd, vec_ok, rows, n_tiles, grid1, lse, rows, s));
+        FV_HIP(run_lse(c, precision, Fx, vec_ok, rows, n_tiles, grid1, lse, rows, s));
         const int groups = normext_groups(c);
         const int grid2 = xcd_grid(std::max(1, std::min(n_items, (device_cu_count(gmm->device) + groups - 1) / groups)));
-        FV_HIP(run_normext(c, precision, Xd, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
+        FV_HIP(run_normext(c, precision, Fx, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
       }
       timing_end(t0, 0, s);
     }
@@ -947,12 +981,146 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
   key.out = Od;
   key.dev = ws->dev;
   key.pinned = ws->pinned;
+  key.pca = pca;
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   FV_HIP(hipEventRecord(ws->pin_done, s));
   ws->pin_pending = true;
   if (!(flags & FV_OUT_DEVICE))
     FV_HIP(hipMemcpyAsync(out, Od, (size_t)B * out_len * 4, hipMemcpyDeviceToHost, s));
+  if (!(flags & FV_ASYNC)) FV_HIP(hipStreamSynchronize(s));
+  return FV_OK;
+}
+
+int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int precision,
+              unsigned flags, void* hip_stream) {
+  return encode_impl(gmm, nullptr, X, N, out, precision, flags, hip_stream);
+}
+
+int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, int B, float* out,
+                    int precision, unsigned flags, void* hip_stream) {
+  return encode_batch_impl(gmm, nullptr, X, offsets, B, out, precision, flags, hip_stream);
+}
+
+int fv_encode_projected(const fv_gmm* gmm, const fv_pca* pca, const float* X, int64_t N,
+                        float* out, int precision, unsigned flags, void* hip_stream) {
+  if (!pca) return FV_E_INVAL;
+  return encode_impl(gmm, pca, X, N, out, precision, flags, hip_stream);
+}
+
+int fv_encode_batch_projected(const fv_gmm* gmm, const fv_pca* pca, const float* X,
+                              const int64_t* offsets, int B, float* out, int precision,
+                              unsigned flags, void* hip_stream) {
+  if (!pca) return FV_E_INVAL;
+  return encode_batch_impl(gmm, pca, X, offsets, B, out, precision, flags, hip_stream);
+}
+
+int fv_pca_load(int Din, int D, const float* A, const float* mean, int device, fv_pca** out) {
+  if (!out) return FV_E_INVAL;
+  *out = nullptr;
+  if (Din < 1 || D < 1 || !A || !mean) return FV_E_INVAL;
+  for (size_t i = 0; i < (size_t)D * Din; ++i)
+    if (!finite_f(A[i])) return FV_E_INVAL;
+  for (int i = 0; i < Din; ++i)
+    if (!finite_f(mean[i])) return FV_E_INVAL;
+  if (Din > fv::kMaxDin || D > fv::kMaxD) return FV_E_UNSUPPORTED;
+  int ndev = 0;
+  const hipError_t de = hipGetDeviceCount(&ndev);
+  if (de != hipSuccess) return hip_fail(de);
+  if (device < 0 || device >= ndev) return FV_E_INVAL;
+
+  fv::ProjConsts p{};
+  p.Din = Din;
+  p.D = D;
+  p.S = (Din + 31) / 32 * 16;
+  p.Dp = (D + 31) / 32 * 32;
+  // operand rows k = 0..2S-1 (input features), columns c = 0..Dp-1 (outputs); bias = -A m in
+  // double, rounded once
+  std::vector<float> frag((size_t)2 * p.S * p.Dp, 0.f), bias((size_t)p.Dp, 0.f);
+  for (int c = 0; c < D; ++c) {
+    double am = 0.0;
+    for (int k = 0; k < Din; ++k) {
+      frag[(size_t)k * p.Dp + c] = A[(size_t)c * Din + k];
+      am += (double)A[(size_t)c * Din + k] * (double)mean[k];
+    }
+    bias[c] = (float)(-am);
+  }
+  const size_t oF = 0, oB = align256(frag.size() * 4), total = oB + align256(bias.size() * 4);
+  DeviceGuard g(device);
+  if (g.status() != hipSuccess) return hip_fail(g.status());
+  std::unique_ptr<fv_pca> h(new (std::nothrow) fv_pca());
+  if (!h) return FV_E_NOMEM;
+  char* blk = nullptr;
+  FV_HIP(hipMalloc(&blk, total));
+  hipError_t e = hipMemcpy(blk + oF, frag.data(), frag.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(blk + oB, bias.data(), bias.size() * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(blk);
+    return hip_fail(e);
+  }
+  p.frag = reinterpret_cast<const float*>(blk + oF);
+  p.bias = reinterpret_cast<const float*>(blk + oB);
+  h->Din = Din;
+  h->D = D;
+  h->device = device;
+  h->p = p;
+  h->dev_block = blk;
+  *out = h.release();
+  return FV_OK;
+}
+
+int fv_pca_free(fv_pca* pca) {
+  if (!pca) return FV_OK;
+  int rc = FV_OK;
+  {
+    DeviceGuard g(pca->device);
+    if (pca->dev_block) {
+      hipError_t e = hipFree(pca->dev_block);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+  }
+  delete pca;
+  return rc;
+}
+
+int fv_pca_info(const fv_pca* pca, int* Din, int* D, int* device) {
+  if (!pca) return FV_E_INVAL;
+  if (Din) *Din = pca->Din;
+  if (D) *D = pca->D;
+  if (device) *device = pca->device;
+  return FV_OK;
+}
+
+int fv_project(const fv_pca* pca, const float* X, int64_t N, float* Y, unsigned flags,
+               void* hip_stream) {
+  if (!pca || N < 0 || (N > 0 && (!X || !Y))) return FV_E_INVAL;
+  if (flags & ~(FV_X_DEVICE | FV_OUT_DEVICE | FV_ASYNC)) return FV_E_INVAL;
+  if (N > ((int64_t)1 << 40) / std::max(pca->Din, pca->D)) return FV_E_UNSUPPORTED;
+  if (N == 0) return FV_OK;
+  DeviceGuard g(pca->device);
+  if (g.status() != hipSuccess) return hip_fail(g.status());
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  Workspace* ws = workspace_for(pca->device, s);
+  if (!ws) return FV_E_NOMEM;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)N * pca->Din * 4);
+  const size_t b_y = (flags & FV_OUT_DEVICE) ? 0 : align256((size_t)N * pca->D * 4);
+  int rc = ensure_dev(ws, b_x + b_y, s);
+  if (rc) return rc;
+  const float* Xd = X;
+  if (!(flags & FV_X_DEVICE)) {
+    float* xdev = reinterpret_cast<float*>(ws->dev);
+    FV_HIP(hipMemcpyAsync(xdev, X, (size_t)N * pca->Din * 4, hipMemcpyHostToDevice, s));
+    Xd = xdev;
+  }
+  if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
+  float* Yd = (flags & FV_OUT_DEVICE) ? Y : reinterpret_cast<float*>(ws->dev + b_x);
+  if ((reinterpret_cast<uintptr_t>(Yd) & 3) != 0) return FV_E_INVAL;
+  hipEvent_t tp = timing_begin(s);
+  FV_HIP(fv::launch_project(pca->p, Xd, N, Yd, project_grid(pca->device, N), s));
+  timing_end(tp, 2, s);
+  if (!(flags & FV_OUT_DEVICE))
+    FV_HIP(hipMemcpyAsync(Y, Yd, (size_t)N * pca->D * 4, hipMemcpyDeviceToHost, s));
   if (!(flags & FV_ASYNC)) FV_HIP(hipStreamSynchronize(s));
   return FV_OK;
 }

@@ -156,7 +156,25 @@ FV_DECLARE_FORM(f16s)
 FV_DECLARE_FORM(bf16)
 #undef FV_DECLARE_FORM
 
+// Projection prologue y = A (x - m) (fv_project.hip).
+constexpr int kMaxDin = 256;
+struct ProjConsts {
+  int Din, D;
+  int S;   // MFMA steps: Din rounded up to a multiple of 32, halved (operand rows 0..2S-1)
+  int Dp;  // D rounded up to a multiple of 32
+  const float* frag;  // [2S][Dp], frag[k][c] = A[c][k] (zero for k >= Din or c >= D)
+  const float* bias;  // [Dp], -(A m)[c] computed in double (zero for c >= D)
+};
+hipError_t launch_project(const ProjConsts& p, const float* X, int64_t N, float* Y, int grid,
+                          hipStream_t stream);
+
 }  // namespace fv
+
+struct fv_pca {
+  int Din = 0, D = 0, device = 0;
+  fv::ProjConsts p{};
+  void* dev_block = nullptr;
+};
 
 // The public handle (opaque in the C ABI).
 struct fv_gmm {

@@ -23,7 +23,9 @@ EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "f
                     "fv_kernel_timing", "fv_kernel_timing_read", "fv_server_config_default", "fv_server_create", "fv_server_destroy",
                     "fv_server_submit", "fv_server_submit_device", "fv_server_poll",
                     "fv_server_next_done",
-                    "fv_server_get_stats", "fv_strerror", "fv_last_device_error")
+                    "fv_server_get_stats", "fv_strerror", "fv_last_device_error",
+                    "fv_pca_load", "fv_pca_free", "fv_pca_info", "fv_project",
+                    "fv_encode_projected", "fv_encode_batch_projected")
 EXEC_HIP, EXEC_FAKE = 0, 1
 
 
@@ -91,6 +93,12 @@ def load():
     lib.fv_gmm_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.fv_encode.argtypes = [vp, vp, i64, vp, i32, u32, vp]
     lib.fv_encode_batch.argtypes = [vp, vp, vp, i32, vp, i32, u32, vp]
+    lib.fv_pca_load.argtypes = [i32, i32, vp, vp, i32, ctypes.POINTER(vp)]
+    lib.fv_pca_free.argtypes = [vp]
+    lib.fv_pca_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.fv_project.argtypes = [vp, vp, i64, vp, u32, vp]
+    lib.fv_encode_projected.argtypes = [vp, vp, vp, i64, vp, i32, u32, vp]
+    lib.fv_encode_batch_projected.argtypes = [vp, vp, vp, vp, i32, vp, i32, u32, vp]
     lib.fv_gmm_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.fv_gmm_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.fv_gmm_set_tuning.restype = i32
@@ -113,6 +121,9 @@ def load():
     lib.fv_strerror.argtypes = [i32]
     lib.fv_strerror.restype = ctypes.c_char_p
     lib.fv_last_device_error.argtypes = []
+    for f in (lib.fv_pca_load, lib.fv_pca_free, lib.fv_pca_info, lib.fv_project,
+              lib.fv_encode_projected, lib.fv_encode_batch_projected):
+        f.restype = i32
     for f in (lib.fv_gmm_load, lib.fv_gmm_free, lib.fv_gmm_info, lib.fv_encode,
               lib.fv_encode_batch, lib.fv_kernel_timing, lib.fv_kernel_timing_read,
               lib.fv_last_device_error):
@@ -235,12 +246,14 @@ def _stream_handle(stream, device: int):
     return stream.cuda_stream
 
 
-def _marshal_x(g: Gmm, X):
-    """Returns (pointer, rows, is_device, keepalive)."""
+def _marshal_x(g, X, width: int | None = None):
+    """Returns (pointer, rows, is_device, keepalive).  Rows have `width` values (g.D by
+    default)."""
+    width = g.D if width is None else width
     if _is_torch(X):
         import torch
-        if X.dtype != torch.float32 or X.dim() != 2 or X.shape[1] != g.D:
-            raise ValueError("X must be a float32 [N, D] tensor")
+        if X.dtype != torch.float32 or X.dim() != 2 or X.shape[1] != width:
+            raise ValueError(f"X must be a float32 [N, {width}] tensor")
         if not X.is_contiguous():
             raise ValueError("X must be contiguous")
         if X.is_cuda:
@@ -250,8 +263,8 @@ def _marshal_x(g: Gmm, X):
         Xc = X.numpy()
         return Xc.ctypes.data, Xc.shape[0], False, Xc
     Xn = _host_f32(X)
-    if Xn.ndim != 2 or Xn.shape[1] != g.D:
-        raise ValueError("X must be [N, D]")
+    if Xn.ndim != 2 or Xn.shape[1] != width:
+        raise ValueError(f"X must be [N, {width}]")
     return Xn.ctypes.data, Xn.shape[0], False, Xn
 
 
@@ -309,6 +322,105 @@ def encode_batch(g: Gmm, X, offsets, out=None, precision: int = PREC_FP32, flags
                                 ctypes.c_void_p(off.ctypes.data), int(B), ctypes.c_void_p(op),
                                 int(precision), f, ctypes.c_void_p(s))
     _check(rc, "fv_encode_batch")
+    return out
+
+
+class Pca:
+    """Owning wrapper of an ``fv_pca*`` (projection prologue y = A (x - m))."""
+
+    def __init__(self, handle: int, Din: int, D: int, device: int):
+        self.handle, self.Din, self.D, self.device = handle, Din, D, device
+
+    def free(self):
+        if self.handle:
+            _check(load().fv_pca_free(ctypes.c_void_p(self.handle)), "fv_pca_free")
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.fv_pca_free(ctypes.c_void_p(self.handle))
+                self.handle = 0
+        except Exception:
+            pass
+
+
+def pca_load(A, mean, device: int = 0) -> Pca:
+    """fv_pca_load: A [D, Din], mean [Din] (host arrays)."""
+    A = _host_f32(A)
+    if A.ndim != 2:
+        raise ValueError("A must be [D, Din]")
+    D, Din = A.shape
+    m = _host_f32(mean, (Din,))
+    h = ctypes.c_void_p()
+    _check(load().fv_pca_load(Din, D, A.ctypes.data, m.ctypes.data, int(device), ctypes.byref(h)),
+           "fv_pca_load")
+    return Pca(h.value, Din, D, int(device))
+
+
+def project(p: Pca, X, out=None, stream=None):
+    """fv_project: [N, Din] -> [N, D] (device tensors in, device tensor out; host arrays in,
+    host array out)."""
+    xp, n, xdev, _keep = _marshal_x(p, X, p.Din)
+    shape = (n, p.D)
+    if out is None:
+        if xdev:
+            import torch
+            out = torch.empty(shape, dtype=torch.float32, device=f"cuda:{p.device}")
+        else:
+            out = np.empty(shape, dtype=np.float32)
+    if _is_torch(out):
+        if tuple(out.shape) != shape or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float32 tensor of shape {shape}")
+        op, odev = out.data_ptr(), out.is_cuda
+        if not odev:
+            op = out.numpy().ctypes.data
+    else:
+        if out.dtype != np.float32 or out.shape != shape or not out.flags.c_contiguous:
+            raise ValueError(f"out must be a contiguous float32 array of shape {shape}")
+        op, odev = out.ctypes.data, False
+    f = (X_DEVICE if xdev else 0) | (OUT_DEVICE if odev else 0)
+    s = _stream_handle(stream, p.device) if (xdev or odev or stream is not None) else 0
+    _check(load().fv_project(ctypes.c_void_p(p.handle), ctypes.c_void_p(xp), int(n),
+                             ctypes.c_void_p(op), f, ctypes.c_void_p(s)), "fv_project")
+    return out
+
+
+def encode_projected(g: Gmm, p: Pca, X, out=None, precision: int = PREC_FP32, flags: int = 0,
+                     stream=None):
+    """fv_encode_projected: X holds raw [N, Din] descriptors."""
+    xp, n, xdev, _keep = _marshal_x(p, X, p.Din)
+    out, op, odev = _marshal_out(g, out, None, xdev)
+    f = int(flags) & ~(X_DEVICE | OUT_DEVICE)
+    f |= (X_DEVICE if xdev else 0) | (OUT_DEVICE if odev else 0)
+    s = _stream_handle(stream, g.device) if (xdev or odev or stream is not None) else 0
+    _check(load().fv_encode_projected(ctypes.c_void_p(g.handle), ctypes.c_void_p(p.handle),
+                                      ctypes.c_void_p(xp), int(n), ctypes.c_void_p(op),
+                                      int(precision), f, ctypes.c_void_p(s)),
+           "fv_encode_projected")
+    return out
+
+
+def encode_batch_projected(g: Gmm, p: Pca, X, offsets, out=None, precision: int = PREC_FP32,
+                           flags: int = 0, stream=None):
+    """fv_encode_batch_projected: X holds raw [sum N, Din] descriptors."""
+    xp, n, xdev, _keep = _marshal_x(p, X, p.Din)
+    if _is_torch(offsets):
+        offsets = offsets.cpu().numpy()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or off.size < 1:
+        raise ValueError("offsets must be a 1-D int64 array of B+1 entries")
+    B = off.size - 1
+    if B > 0 and off[-1] != n:
+        raise ValueError("offsets[-1] must equal the number of rows of X")
+    out, op, odev = _marshal_out(g, out, B, xdev)
+    f = int(flags) & ~(X_DEVICE | OUT_DEVICE)
+    f |= (X_DEVICE if xdev else 0) | (OUT_DEVICE if odev else 0)
+    s = _stream_handle(stream, g.device) if (xdev or odev or stream is not None) else 0
+    _check(load().fv_encode_batch_projected(ctypes.c_void_p(g.handle), ctypes.c_void_p(p.handle),
+                                            ctypes.c_void_p(xp), ctypes.c_void_p(off.ctypes.data),
+                                            int(B), ctypes.c_void_p(op), int(precision), f,
+                                            ctypes.c_void_p(s)), "fv_encode_batch_projected")
     return out
 
 

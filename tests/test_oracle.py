@@ -8,6 +8,7 @@ import pytest
 import oracle
 from oracle import brute
 import oracle_pins as P
+from oracle.metrics import errors
 
 
 @pytest.fixture(scope="module")
@@ -111,3 +112,28 @@ def test_pins_catch_planted_mistake(name):
             except Exception:
                 caught.append(pin.__name__ + "(error)")
         assert caught, f"no pin catches mutant {name}"
+
+
+def test_projection_brute_force_and_recovery():
+    """oracle.project against a pure-Python loop on a tiny input (brute force), and on a
+    synthetic raw frame it returns the GMM sample the frame was built from."""
+    import fvsynth
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((3, 5)).astype(np.float32)
+    m = rng.standard_normal(5).astype(np.float32)
+    X = rng.standard_normal((4, 5)).astype(np.float32)
+    got = oracle.project(X, A, m)
+    for t in range(4):
+        for c in range(3):
+            ref = 0.0
+            for k in range(5):
+                ref += float(A[c, k]) * (float(X[t, k]) - float(m[k]))
+            assert abs(got[t, c] - ref) <= 1e-14 * (1 + abs(ref))
+    g = fvsynth.gmm(16, 64, 1)
+    p = fvsynth.pca(64, 2)
+    Xr = fvsynth.raw_frame(g, p, 300, 5, 0.05)
+    y = fvsynth.frame(g, 300, 5, 0.05)
+    assert np.max(np.abs(oracle.project(Xr, p.A, p.mean) - y)) < 2e-6
+    # and the FV of the float64 projection agrees with the FV of the float32 sample it came from
+    e = errors(oracle.encode_projected(Xr, p.A, p.mean, g), oracle.encode_gmm(y, g))
+    assert e["e_2"] < 1e-4

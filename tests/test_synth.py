@@ -35,6 +35,21 @@ def test_frame_recipe():
     assert sizes.min() >= 2000 and sizes.max() <= 20000 and len(sizes) == 64
 
 
+def test_pca_recipe():
+    g = fvsynth.gmm(32, 64, 0)
+    p = fvsynth.pca(64, 0)
+    assert p.A.shape == (64, 130) and p.mean.shape == (130,) and p.A.dtype == np.float32
+    Q = p.A[:62, :128].astype(np.float64)
+    assert np.allclose(Q @ Q.T, np.eye(62), atol=1e-6)           # orthonormal rows
+    assert np.array_equal(p.A[62:, 128:], np.eye(2, dtype=np.float32))  # coordinates pass
+    assert np.all(p.A[62:, :128] == 0) and np.all(p.A[:62, 128:] == 0) and np.all(p.mean[128:] == 0)
+    X = fvsynth.raw_frame(g, p, 500, 3, 0.05)
+    assert X.shape == (500, 130) and X.dtype == np.float32
+    # the coordinates are the last two dimensions of the GMM sample, unchanged
+    y = fvsynth.frame(g, 500, 3, 0.05)
+    assert np.array_equal(X[:, 128:], y[:, 62:])
+
+
 def test_serving_plan():
     ev, sizes = fvsynth.serving_plan(duration_s=2.0)
     assert sizes[:5] == [8000, 12500, 18000, 24500, 32000]
