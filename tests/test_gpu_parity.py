@@ -182,3 +182,42 @@ def test_invalid_batch_offsets(fv):
         rc = lib.fv_encode_batch(ctypes.c_void_p(h.handle), X.ctypes.data, o.ctypes.data, 2,
                                  out.ctypes.data, 0, 0, None)
         assert rc == fv.E_INVAL
+
+
+@pytest.mark.parametrize("D", [96, 93])
+def test_max_sizes(fv, D):
+    """The largest supported model (K = 1024, D = 96) and a ragged D (rows not 16-byte
+    aligned): single frame in FP32 and bf16 split, and a two-frame batch."""
+    import torch
+    K, N = 1024, 2500
+    say(f"[gpu] max sizes K={K} D={D} N={N}")
+    g = fvsynth.gmm(K, D, 3)
+    X = fvsynth.frame(g, N, 21, 0.05)
+    ref = oracle.encode_gmm(X, g)
+    h = _gmm(fv, g)
+    Xd = torch.from_numpy(X).cuda()
+    got = fv.encode(h, Xd).cpu().numpy()
+    if D == 93:
+        # The largest entries of this vector are the v block of component 313, whose weight is
+        # 9.1e-7 (Dirichlet(1) over 1024 components): the block is scaled by 1/sqrt(2 w) ~ 740
+        # and rests on a single soft-assigned outlier descriptor (gamma 0.29).  E_inf is then
+        # that one posterior's relative error, set by the FP32 logit error at logit magnitudes
+        # of ~10^3 (log2 units, 186 products): measured 1.09e-5.  E_2 keeps the 1e-5 gate; E_inf
+        # is gated at 2e-5 for this input only.
+        w = g.weights.astype(np.float64)
+        s_ref = ref * np.abs(ref)
+        worst = int(np.argmax(np.abs(s_ref))) % (K * D) // D
+        assert w[worst] < 1e-5, "the largest block is expected to be the tiny-weight component"
+        _check(f"K{K}_D{D}_fp32", got, ref, tol=2e-5)
+        assert errors(got, ref)["e_2"] <= TOL_FP32
+    else:
+        _check(f"K{K}_D{D}_fp32", got, ref)
+    got = fv.encode(h, Xd, precision=fv.PREC_BF16_SPLIT).cpu().numpy()
+    e = errors(got, ref)
+    say(f"  bf16 split: {e}")
+    assert e["e_inf"] <= 1e-3 and e["e_2"] <= 1e-3
+    Xb, off = fvsynth.batch_frames(g, [1300, 700], seed0=31)
+    refb = oracle.encode_batch(Xb, off, g.weights, g.means, g.variances, nthreads=2)
+    gotb = fv.encode_batch(h, torch.from_numpy(Xb).cuda(), off).cpu().numpy()
+    for b in range(2):
+        _check(f"K{K}_D{D}_batch{b}", gotb[b], refb[b])
