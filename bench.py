@@ -158,6 +158,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch with the default tuning instead of the measuring autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-em", action="store_true", help="skip the EM-step measurement")
     ap.add_argument("--no-projection", action="store_true",
                     help="skip the projection-prologue measurements")
     ap.add_argument("--no-paper-mode", action="store_true",
@@ -579,6 +580,26 @@ def main():
             fv.set_tuning(hb)
         hp.free()
 
+    # EM training step on the batch's descriptors as one training set (the encoder's first
+    # pass and statistics pass, then the M-step and log-likelihood reductions)
+    em = {}
+    if not a.no_em and batch:
+        for form in forms:
+            Xbd_ = Xbd
+            for _ in range(2):
+                fv.em_step(hb, Xbd_, precision=PREC_CODE[form], var_floor=1e-3, stream=stream)
+            steps = max(3, a.batch_steps // 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fv.em_step(hb, Xbd_, precision=PREC_CODE[form], var_floor=1e-3, stream=stream)
+            el = time.perf_counter() - t0
+            nb = int(Xbd_.shape[0])
+            em[form] = {"value": nb * steps / el, "ms_per_step": el * 1e3 / steps,
+                        "descriptors": nb}
+            log(f"[bench] em step form={form}: {nb * steps / el:.4e} desc/s, "
+                f"{el * 1e3 / steps:.3f} ms/step")
+
     serving = []
     if a.serving_seconds > 0:
         for budget in (2 << 30, 64 << 20):
@@ -639,6 +660,11 @@ def main():
         result["serving_sweep"] = sweep
     if c5:
         result["c5_capacity_device_input"] = c5
+    if em:
+        result["em_step"] = {
+            "forms": em,
+            "note": "one EM iteration (host-returned model and log-likelihood) over all rows of "
+                    "the 64-frame batch as one training set, K = 256, D = 64"}
     if projected:
         result["projected_din130"] = {
             "forms": projected,

@@ -191,6 +191,25 @@ int fv_encode_batch_projected(const fv_gmm* gmm, const fv_pca* pca, const float*
                               const int64_t* offsets, int B, float* out, int precision,
                               unsigned flags, void* hip_stream);
 
+/* ---- training step -------------------------------------------------------------------- */
+/*
+ * One EM iteration for the GMM (the model the encoder uses is trained beforehand, Sec. 3.1).
+ * The E-step and the sums are the encoder's own kernels (first pass: per-row normalisers;
+ * statistics pass: S0 = sum_t gamma_tk, S1 = gamma^T X, S2 = gamma^T X^2, precision as for
+ * fv_encode); then, in double on the device:
+ *   w_k = S0_k / N,   mu_kd = S1_kd / S0_k,   var_kd = max(S2_kd / S0_k - mu_kd^2, var_floor)
+ * (a component with S0_k = 0 gets w_k = 0, mu_k = 0, var_k = var_floor; such a model is not
+ * loadable until the caller re-seeds it), and the log-likelihood of X under the current model,
+ *   loglik = sum_t ln sum_k w_k N(x_t; mu_k, diag var_k).
+ * X [N x D] float32 row-major, host or device (FV_X_DEVICE; no other flag).  Outputs are host
+ * arrays: weights [K], means [K x D], variances [K x D] (float32), *loglik (double).  Returns
+ * after the stream has finished.  Errors: FV_E_INVAL (null pointers, N < 1, bad precision,
+ * flags, negative or non-finite var_floor), FV_E_NOMEM, FV_E_DEVICE.
+ */
+int fv_em_step(const fv_gmm* gmm, const float* X, int64_t N, int precision, float var_floor,
+               unsigned flags, void* hip_stream, float* weights, float* means, float* variances,
+               double* loglik);
+
 /* ---- serving ------------------------------------------------------------------------------
  * A server keeps one GMM and its own HIP streams, accepts frames of any size from any thread,
  * and encodes them with continuous batching: a scheduler thread admits queued requests in

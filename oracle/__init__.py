@@ -188,3 +188,33 @@ def project(X, A, mean) -> np.ndarray:
 def encode_projected(X, A, mean, g, flags: int = 0, tau: float | None = None) -> np.ndarray:
     """Fisher vector of the projected descriptors, the projection kept in float64."""
     return _load().encode_f64(project(X, A, mean), g.weights, g.means, g.variances, flags, tau)
+
+
+def em_step(X, weights, means, variances, var_floor: float = 1e-6, lib: OracleLib | None = None):
+    """One EM iteration in float64 (the training the paper does beforehand, Sec. 3.1), by
+    definition: gamma from the oracle's posteriors (steps 1-4); n_k = sum_t gamma_tk;
+    w_k = n_k / N; mu_k = sum_t gamma_tk x_t / n_k; var_kd = max(sum_t gamma_tk (x_td -
+    mu_kd)^2 / n_k, floor) (a component with n_k = 0: w = 0, mu = 0, var = floor); and the
+    log-likelihood sum_t ln sum_k w_k N(x_t; mu_k, var_k) of the input model, with the
+    log-sum-exp taken by scipy.  Returns (w, mu, var, loglik) in float64."""
+    from scipy.special import logsumexp
+    X64 = np.asarray(X, dtype=np.float32).astype(np.float64)
+    w0 = np.asarray(weights, dtype=np.float32).astype(np.float64)
+    mu0 = np.asarray(means, dtype=np.float32).astype(np.float64)
+    var0 = np.asarray(variances, dtype=np.float32).astype(np.float64)
+    N, D = X64.shape
+    gam = (lib or _load()).posteriors(X, weights, means, variances)
+    nk = gam.sum(axis=0)
+    K = nk.shape[0]
+    w = nk / N
+    mu = np.zeros((K, D))
+    var = np.full((K, D), float(var_floor))
+    for k in range(K):
+        if nk[k] > 0:
+            mu[k] = gam[:, k] @ X64 / nk[k]
+            var[k] = np.maximum(gam[:, k] @ (X64 - mu[k]) ** 2 / nk[k], var_floor)
+    logj = np.empty((N, K))
+    for k in range(K):
+        logj[:, k] = (np.log(w0[k]) - 0.5 * np.log(2 * np.pi * var0[k]).sum()
+                      - 0.5 * (((X64 - mu0[k]) ** 2) / var0[k]).sum(axis=1))
+    return w, mu, var, float(logsumexp(logj, axis=1).sum())

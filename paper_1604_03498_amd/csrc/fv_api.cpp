@@ -1125,4 +1125,77 @@ int fv_project(const fv_pca* pca, const float* X, int64_t N, float* Y, unsigned 
   return FV_OK;
 }
 
+int fv_em_step(const fv_gmm* gmm, const float* X, int64_t N, int precision, float var_floor,
+               unsigned flags, void* hip_stream, float* weights, float* means, float* variances,
+               double* loglik) {
+  if (!gmm || N < 1 || !X || !weights || !means || !variances || !loglik) return FV_E_INVAL;
+  if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
+  if (flags & ~(unsigned)FV_X_DEVICE) return FV_E_INVAL;
+  if (!(var_floor >= 0.f) || !finite_f(var_floor)) return FV_E_INVAL;
+  const fv::Consts c = call_consts(gmm, 0);
+  if (N > ((int64_t)1 << 40) / c.D) return FV_E_UNSUPPORTED;
+  DeviceGuard g(gmm->device);
+  if (g.status() != hipSuccess) return hip_fail(g.status());
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  Workspace* ws = workspace_for(gmm->device, s);
+  if (!ws) return FV_E_NOMEM;
+  std::lock_guard<std::mutex> lk(ws->mu);
+
+  // the encoder's two-pass path: the first pass gives the row normalisers (the likelihood),
+  // the second the per-chunk sums S0, S1, S2
+  const bool grouped = c.Kp > fv::kFusedMaxK;
+  const int slices = c.Kp / fv::kCompsPerWave;
+  const int P = grouped ? normext_single_chunk(N, gmm->device, normext_groups(c))
+                        : split_single_chunk(N, gmm->device, slices, sliced_round(c, precision),
+                                             precision == FV_PREC_FP32 ? 2 : 1);
+  const int n_items = (int)((N + P - 1) / P);
+  const int G = fv::lse_groups(c);
+  const int nll = fv::em_loglik_blocks(N);
+  const size_t KD = (size_t)c.K * c.D;
+  const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
+  const size_t b_lse = align256((size_t)G * N * 8);
+  const size_t b_out = align256((c.K + 2 * KD) * 4);
+  const size_t b_ll = align256((size_t)nll * 8);
+  const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)N * c.D * 4);
+  int rc = ensure_dev(ws, b_part + b_lse + b_out + b_ll + b_x, s);
+  if (rc) return rc;
+  char* base = ws->dev;
+  float* partials = reinterpret_cast<float*>(base);
+  float2* lse = reinterpret_cast<float2*>(base + b_part);
+  float* odev = reinterpret_cast<float*>(base + b_part + b_lse);
+  double* lldev = reinterpret_cast<double*>(base + b_part + b_lse + b_out);
+  float* xdev = reinterpret_cast<float*>(base + b_part + b_lse + b_out + b_ll);
+  const float* Xd = X;
+  if (!(flags & FV_X_DEVICE)) {
+    FV_HIP(hipMemcpyAsync(xdev, X, (size_t)N * c.D * 4, hipMemcpyHostToDevice, s));
+    Xd = xdev;
+  }
+  if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
+  const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
+  const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
+  const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
+  FV_HIP(run_lse(c, precision, Xd, vec_ok, N, n_tiles, grid1, lse, N, s));
+  if (grouped)
+    FV_HIP(run_normext(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
+                       partials, s));
+  else
+    FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
+                      partials, s));
+  FV_HIP(fv::launch_em(c, partials, n_items, N, var_floor, lse, N, odev, odev + c.K,
+                       odev + c.K + KD, lldev, s));
+  std::vector<float> hout(c.K + 2 * KD);
+  std::vector<double> hll((size_t)nll);
+  FV_HIP(hipMemcpyAsync(hout.data(), odev, hout.size() * 4, hipMemcpyDeviceToHost, s));
+  FV_HIP(hipMemcpyAsync(hll.data(), lldev, hll.size() * 8, hipMemcpyDeviceToHost, s));
+  FV_HIP(hipStreamSynchronize(s));
+  std::memcpy(weights, hout.data(), (size_t)c.K * 4);
+  std::memcpy(means, hout.data() + c.K, KD * 4);
+  std::memcpy(variances, hout.data() + c.K + KD, KD * 4);
+  double ll2 = 0.0;
+  for (double v : hll) ll2 += v;
+  // logits are log2-scaled and leave out the -D/2 ln(2 pi) of every Gaussian density
+  *loglik = ll2 * 0.69314718055994530942 - (double)N * 0.5 * c.D * 1.8378770664093454836;
+  return FV_OK;
+}
+
 }  // extern "C"

@@ -168,6 +168,13 @@ struct ProjConsts {
 hipError_t launch_project(const ProjConsts& p, const float* X, int64_t N, float* Y, int grid,
                           hipStream_t stream);
 
+// EM step (fv_em.hip): M-step from the statistics partials, log-likelihood from the first
+// pass's row normalisers (ll_part: em_loglik_blocks(N) workgroup sums, log2 units).
+int em_loglik_blocks(int64_t N);
+hipError_t launch_em(const Consts& c, const float* partials, int n_items, int64_t N,
+                     float var_floor, const float2* lse, int64_t lse_stride, float* w_out,
+                     float* mu_out, float* var_out, double* ll_part, hipStream_t stream);
+
 }  // namespace fv
 
 struct fv_pca {

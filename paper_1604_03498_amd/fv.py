@@ -25,7 +25,7 @@ EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "f
                     "fv_server_next_done",
                     "fv_server_get_stats", "fv_strerror", "fv_last_device_error",
                     "fv_pca_load", "fv_pca_free", "fv_pca_info", "fv_project",
-                    "fv_encode_projected", "fv_encode_batch_projected")
+                    "fv_encode_projected", "fv_encode_batch_projected", "fv_em_step")
 EXEC_HIP, EXEC_FAKE = 0, 1
 
 
@@ -121,8 +121,10 @@ def load():
     lib.fv_strerror.argtypes = [i32]
     lib.fv_strerror.restype = ctypes.c_char_p
     lib.fv_last_device_error.argtypes = []
+    lib.fv_em_step.argtypes = [vp, vp, i64, i32, ctypes.c_float, u32, vp, vp, vp, vp,
+                               ctypes.POINTER(ctypes.c_double)]
     for f in (lib.fv_pca_load, lib.fv_pca_free, lib.fv_pca_info, lib.fv_project,
-              lib.fv_encode_projected, lib.fv_encode_batch_projected):
+              lib.fv_encode_projected, lib.fv_encode_batch_projected, lib.fv_em_step):
         f.restype = i32
     for f in (lib.fv_gmm_load, lib.fv_gmm_free, lib.fv_gmm_info, lib.fv_encode,
               lib.fv_encode_batch, lib.fv_kernel_timing, lib.fv_kernel_timing_read,
@@ -422,6 +424,38 @@ def encode_batch_projected(g: Gmm, p: Pca, X, offsets, out=None, precision: int 
                                             int(B), ctypes.c_void_p(op), int(precision), f,
                                             ctypes.c_void_p(s)), "fv_encode_batch_projected")
     return out
+
+
+def em_step(g: Gmm, X, precision: int = PREC_FP32, var_floor: float = 1e-6, stream=None):
+    """fv_em_step: one EM iteration of the model g on X.  Returns (weights [K], means [K, D],
+    variances [K, D], loglik) as host arrays and a float."""
+    xp, n, xdev, _keep = _marshal_x(g, X)
+    w = np.empty(g.K, np.float32)
+    mu = np.empty((g.K, g.D), np.float32)
+    var = np.empty((g.K, g.D), np.float32)
+    ll = ctypes.c_double()
+    s = _stream_handle(stream, g.device) if (xdev or stream is not None) else 0
+    _check(load().fv_em_step(ctypes.c_void_p(g.handle), ctypes.c_void_p(xp), int(n),
+                             int(precision), float(var_floor), X_DEVICE if xdev else 0,
+                             ctypes.c_void_p(s), w.ctypes.data, mu.ctypes.data, var.ctypes.data,
+                             ctypes.byref(ll)), "fv_em_step")
+    return w, mu, var, ll.value
+
+
+def em_fit(X, weights, means, variances, iters: int, precision: int = PREC_FP32,
+           var_floor: float = 1e-6, device: int = 0, stream=None):
+    """EM iterations from the given model (each step on the device, the new model loaded for
+    the next).  Returns (weights, means, variances, [loglik of each step's input model])."""
+    w, mu, var = (np.asarray(a, np.float32) for a in (weights, means, variances))
+    lls = []
+    for _ in range(int(iters)):
+        g = gmm_load(w, mu, var, device)
+        try:
+            w, mu, var, ll = em_step(g, X, precision, var_floor, stream)
+        finally:
+            g.free()
+        lls.append(ll)
+    return w, mu, var, lls
 
 
 def server_config(**kw) -> ServerConfig:

@@ -15,6 +15,9 @@ raises AssertionError when the oracle disagrees with the fact it checks.  The fa
   not print
 * translation, scaling, negation, component / descriptor permutation, duplication
 * ||phi||_2 == 1 after L2; N = 0 and phi == 0 give zeros                         (definition)
+* EM step: n_k, means and variances == sklearn's diagonal M-step
+  (_estimate_gaussian_parameters, reg_covar 0) on the sklearn posteriors, log-likelihood ==
+  sum of GaussianMixture.score_samples                                          (library)
 * with the posterior threshold tau (Algorithm 1's test), U and V == the autograd
   per-descriptor gradients summed over the (t, k) whose torch posterior exceeds tau
                                                                                  (library)
@@ -145,6 +148,33 @@ def pin_threshold_autograd(o, seed=5, tau=1e-6):
     assert np.max(np.abs(full - phi)) > 1e-9 * np.max(np.abs(full))
 
 
+def pin_em_step_sklearn(o, seed=6):
+    """The oracle's EM step against sklearn's diagonal M-step on sklearn's posteriors and
+    against the summed sklearn log-likelihood of the input model."""
+    import oracle
+    from sklearn.mixture import GaussianMixture
+    from sklearn.mixture._gaussian_mixture import _estimate_gaussian_parameters
+    rng = np.random.default_rng(seed)
+    for K, D, N in ((4, 3, 300), (12, 8, 500)):
+        w = rng.dirichlet(np.ones(K) * 2).astype(np.float32)
+        mu = (rng.standard_normal((K, D)) * 1.5).astype(np.float32)
+        var = rng.uniform(0.5, 2.0, (K, D)).astype(np.float32)
+        X = (mu[rng.integers(0, K, N)] + rng.standard_normal((N, D))).astype(np.float32)
+        X64 = X.astype(np.float64)
+        gm = GaussianMixture(n_components=K, covariance_type="diag")
+        gm.weights_ = w.astype(np.float64)
+        gm.means_ = mu.astype(np.float64)
+        gm.covariances_ = var.astype(np.float64)
+        gm.precisions_cholesky_ = 1.0 / np.sqrt(var.astype(np.float64))
+        nk, m_ref, v_ref = _estimate_gaussian_parameters(X64, gm.predict_proba(X64), 0.0, "diag")
+        w1, m1, v1, ll = oracle.em_step(X, w, mu, var, var_floor=0.0, lib=o)
+        assert np.max(np.abs(w1 - nk / N)) < 1e-12
+        assert np.max(np.abs(m1 - m_ref)) < 1e-10 * np.max(np.abs(m_ref))
+        assert np.max(np.abs(v1 - v_ref) / v_ref) < 1e-9
+        ll_ref = gm.score_samples(X64).sum()
+        assert abs(ll - ll_ref) < 1e-10 * abs(ll_ref), (ll, ll_ref)
+
+
 def pin_single_component(o, seed=2):
     rng = np.random.default_rng(seed)
     for D, N, wk in ((5, 300, 1.0), (7, 64, 0.37)):
@@ -264,4 +294,4 @@ def pin_normalisation(o, seed=4):
 
 ALL_PINS = (pin_posteriors_sklearn, pin_posteriors_logistic, pin_gradient_autograd,
             pin_single_component, pin_on_means, pin_unit_variance, pin_invariances,
-            pin_normalisation, pin_threshold_autograd)
+            pin_normalisation, pin_threshold_autograd, pin_em_step_sklearn)

@@ -123,6 +123,15 @@ def test_pca_validation_without_device():
                                          out.ctypes.data, 0, 0, None) == fv.E_INVAL
 
 
+def test_em_step_validation_without_device():
+    lib = fv.load()
+    X = np.zeros((2, 2), np.float32)
+    o = np.zeros(8, np.float32)
+    ll = ctypes.c_double()
+    assert lib.fv_em_step(None, X.ctypes.data, 2, 0, 1e-3, 0, None, o.ctypes.data, o.ctypes.data,
+                          o.ctypes.data, ctypes.byref(ll)) == fv.E_INVAL
+
+
 def test_binding_refuses_missing_library(tmp_path, monkeypatch):
     import paper_1604_03498_amd.fv as mod
     monkeypatch.setattr(mod, "_lib", None)
