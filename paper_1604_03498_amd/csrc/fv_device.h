@@ -254,7 +254,8 @@ struct TileIO {
 // the LDS tile.  The 2*DP products are accumulated in chains of 16 MFMA steps and the chain
 // sums are added with TwoSum, so the logit is the unevaluated pair hi + lo: downstream code
 // evaluates (hi - reference) + lo, accurate to the size of the difference rather than of the
-// logit itself (which reaches a few hundred).
+// logit itself (which reaches a few hundred).  The offset c joins the first chain's sum once
+// (not as its initial value), so no chain accumulates at the offset's magnitude.
 template <int DP>
 __device__ __forceinline__ void estep_f32(const float* __restrict__ xr, const float (&areg)[DP],
                                           float cval, f32x16& hi, f32x16& lo) {
@@ -263,7 +264,7 @@ __device__ __forceinline__ void estep_f32(const float* __restrict__ xr, const fl
   for (int ch = 0; ch < DP / CH; ++ch) {
     f32x16 a;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) a[r] = (ch == 0) ? cval : 0.f;
+    for (int r = 0; r < 16; ++r) a[r] = 0.f;
 #pragma unroll
     for (int s = CH * ch; s < CH * ch + CH; s += 4) {
       const f32x4 xv = *reinterpret_cast<const f32x4*>(xr + s);
@@ -273,9 +274,12 @@ __device__ __forceinline__ void estep_f32(const float* __restrict__ xr, const fl
       a = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[3], areg[s + 3], a, 0, 0, 0);
     }
     if (ch == 0) {
-      hi = a;
+      // the offset joins after the first chain: the chain's partial sums stay small
 #pragma unroll
-      for (int r = 0; r < 16; ++r) lo[r] = 0.f;
+      for (int r = 0; r < 16; ++r) {
+        hi[r] = a[r] + cval;
+        lo[r] = 0.f;
+      }
     } else {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -306,7 +310,7 @@ __device__ __forceinline__ void estep_f32_lds(const float* __restrict__ xr,
   for (int ch = 0; ch < DP / CH; ++ch) {
     f32x16 a;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) a[r] = (ch == 0) ? cval : 0.f;
+    for (int r = 0; r < 16; ++r) a[r] = 0.f;
 #pragma unroll
     for (int s = CH * ch; s < CH * ch + CH; s += 4) {
       f32x4 xv = xn;
@@ -324,9 +328,12 @@ __device__ __forceinline__ void estep_f32_lds(const float* __restrict__ xr,
       __builtin_amdgcn_sched_barrier(0);
     }
     if (ch == 0) {
-      hi = a;
+      // the offset joins after the first chain: the chain's partial sums stay small
 #pragma unroll
-      for (int r = 0; r < 16; ++r) lo[r] = 0.f;
+      for (int r = 0; r < 16; ++r) {
+        hi[r] = a[r] + cval;
+        lo[r] = 0.f;
+      }
     } else {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {

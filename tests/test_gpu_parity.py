@@ -196,22 +196,10 @@ def test_max_sizes(fv, D):
     ref = oracle.encode_gmm(X, g)
     h = _gmm(fv, g)
     Xd = torch.from_numpy(X).cuda()
-    got = fv.encode(h, Xd).cpu().numpy()
-    if D == 93:
-        # The largest entries of this vector are the v block of component 313, whose weight is
-        # 9.1e-7 (Dirichlet(1) over 1024 components): the block is scaled by 1/sqrt(2 w) ~ 740
-        # and rests on a single soft-assigned outlier descriptor (gamma 0.29).  E_inf is then
-        # that one posterior's relative error, set by the FP32 logit error at logit magnitudes
-        # of ~10^3 (log2 units, 186 products): measured 1.09e-5.  E_2 keeps the 1e-5 gate; E_inf
-        # is gated at 2e-5 for this input only.
-        w = g.weights.astype(np.float64)
-        s_ref = ref * np.abs(ref)
-        worst = int(np.argmax(np.abs(s_ref))) % (K * D) // D
-        assert w[worst] < 1e-5, "the largest block is expected to be the tiny-weight component"
-        _check(f"K{K}_D{D}_fp32", got, ref, tol=2e-5)
-        assert errors(got, ref)["e_2"] <= TOL_FP32
-    else:
-        _check(f"K{K}_D{D}_fp32", got, ref)
+    # D = 93 is ill-conditioned at this model: the largest entries are the v block of a
+    # component of weight 9.1e-7 (scaled by 1/sqrt(2w) ~ 740) resting on one soft-assigned
+    # outlier descriptor, so E_inf is that posterior's FP32 relative error
+    _check(f"K{K}_D{D}_fp32", fv.encode(h, Xd).cpu().numpy(), ref)
     got = fv.encode(h, Xd, precision=fv.PREC_BF16_SPLIT).cpu().numpy()
     e = errors(got, ref)
     say(f"  bf16 split: {e}")
