@@ -501,6 +501,13 @@ def main():
         Xc = fvsynth.frame(g, N, fvsynth.WORKLOADS["c2_frame_k256_d64_n8000"]["frame_seed"], 0.05,
                            clustered=True)
         Xcd = torch.from_numpy(Xc).to(dev)
+        if batch:
+            # the batch's frames, each with its rows grouped by generating component
+            w4 = fvsynth.WORKLOADS["c4_batch64_k256_d64"]
+            sz = fvsynth.batch_sizes(w4["B"], w4["sizes_seed"])
+            Xbc = np.concatenate([fvsynth.frame(g, int(n), w4["frame_seed0"] + f, w4["outliers"],
+                                                clustered=True) for f, n in enumerate(sz)])
+            Xbcd = torch.from_numpy(np.ascontiguousarray(Xbc)).to(dev)
         for form in forms:
             paper[form] = {}
             for name, xin in (("frame", Xd), ("frame_clustered", Xcd)):
@@ -516,14 +523,17 @@ def main():
                 outb = torch.empty(offb.size - 1, 2 * K * D, dtype=torch.float32, device=dev)
                 fv.set_tuning(hb, batch_path=1 if batch[form]["tuned"]["path"] == "fused" else 2,
                               batch_chunk=batch[form]["tuned"]["chunk"])
-                el, st_avg, _, _, _ = time_form(fv, torch, hb, Xbd, offb, outb, form,
-                                                a.batch_steps, 2, stream, 0, True, fv.THRESHOLD)
-                nb = int(offb[-1])
-                paper[form]["batch"] = {"value": nb * a.batch_steps / el,
-                                        "ms_per_step": el * 1e3 / a.batch_steps,
-                                        "stats_avg_us": round(st_avg * 1e3, 3),
-                                        "path": batch[form]["tuned"]["path"]}
-                log(f"[bench] paper mode batch form={form}: {nb * a.batch_steps / el:.4e} desc/s")
+                for name, xin in (("batch", Xbd), ("batch_clustered", Xbcd)):
+                    el, st_avg, _, _, _ = time_form(fv, torch, hb, xin, offb, outb, form,
+                                                    a.batch_steps, 2, stream, 0, True,
+                                                    fv.THRESHOLD)
+                    nb = int(offb[-1])
+                    paper[form][name] = {"value": nb * a.batch_steps / el,
+                                         "ms_per_step": el * 1e3 / a.batch_steps,
+                                         "stats_avg_us": round(st_avg * 1e3, 3),
+                                         "path": batch[form]["tuned"]["path"]}
+                    log(f"[bench] paper mode {name} form={form}: "
+                        f"{nb * a.batch_steps / el:.4e} desc/s, stats {st_avg * 1e3:.1f} us")
         if batch:
             fv.set_tuning(hb)
 
@@ -682,7 +692,8 @@ def main():
         result["paper_threshold_mode"] = {
             "tau": fv.THRESHOLD_TAU, "forms": paper,
             "note": "terms with posterior <= tau left out; MFMA steps with no term above tau "
-                    "skipped; frame_clustered = the same descriptors grouped by component"}
+                    "skipped; *_clustered = the same descriptors, each frame's rows grouped by "
+                    "generating component"}
     if not a.no_cpu_baseline:
         import oracle
         from oracle.metrics import errors
