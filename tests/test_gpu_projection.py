@@ -152,3 +152,22 @@ def test_projected_graph_replays_and_mismatch(fv, monkeypatch):
     other = fv.pca_load(np.eye(32, 130, dtype=np.float32), np.zeros(130, np.float32))
     with pytest.raises(fv.FvError):
         fv.encode_projected(h, other, frames[0][:10])
+
+
+def test_projected_threshold_mode(fv):
+    """The projection prologue composes with the posterior threshold: against the oracle's
+    tau mode on the float64 projection."""
+    import torch
+    say("[gpu] projected + threshold")
+    g = fvsynth.gmm(256, 64, 0)
+    p = fvsynth.pca(64, 0)
+    X = fvsynth.raw_frame(g, p, 4000, 17, 0.05)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    hp = fv.pca_load(p.A, p.mean)
+    for prec, tol in ((0, 1e-5), (1, 1e-3)):
+        ref = oracle.encode_projected(X, p.A, p.mean, g, tau=fv.THRESHOLD_TAU)
+        got = fv.encode_projected(h, hp, torch.from_numpy(X).cuda(), precision=prec,
+                                  flags=fv.THRESHOLD).cpu().numpy()
+        e = errors(got, ref)
+        say(f"  prec={prec} e_inf={e['e_inf']:.3e} e_2={e['e_2']:.3e}")
+        assert e["e_inf"] <= tol and e["e_2"] <= tol, e
