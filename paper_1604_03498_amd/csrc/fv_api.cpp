@@ -321,27 +321,36 @@ int path_override() {
 // one 8-wave workgroup per CU at 256 components (register bound), more for fewer waves.
 int resident_fused(int device, int Wg) { return device_cu_count(device) * std::max(1, 8 / Wg); }
 
+// Above DP = 80 the 8-wave FP32 fused kernel spills registers and the two-pass path (whose
+// group-wise second pass runs 4 waves there) is faster: 1.45 against 1.85 ms for 32 frames at
+// K = 256, D = 96.  The 16-bit forms and smaller D keep the fused kernel.
+bool fused_spills(const fv_gmm* g, int precision) {
+  return precision == FV_PREC_FP32 && g->c.DP > 80 && g->c.Wg == fv::kMaxWaves;
+}
+
 // Single frame: the fused kernel needs several 32-row tiles per resident workgroup to amortise
 // its per-chunk partial write; below that the two-pass path (more, smaller workgroups and
 // fewer partial slots) is used.  More than 256 components always take the two-pass path.
-Path choose_single(const fv_gmm* g, int64_t N) {
+Path choose_single(const fv_gmm* g, int64_t N, int precision) {
   const fv::Consts& c = g->c;
   if (c.Kp > fv::kFusedMaxK) return Path::kSplit;
   const int o = path_override();
   if (o == 1) return Path::kFused;
   if (o == 2) return Path::kSplit;
+  if (fused_spills(g, precision) && g->single_split_below == 0) return Path::kSplit;
   const int64_t below = g->single_split_below > 0
                             ? g->single_split_below
                             : (int64_t)4 * fv::kTile * resident_fused(g->device, c.Wg);
   return N < below ? Path::kSplit : Path::kFused;
 }
 
-Path choose_batch(const fv_gmm* g) {
+Path choose_batch(const fv_gmm* g, int precision) {
   if (g->c.Kp > fv::kFusedMaxK) return Path::kSplit;
   const int o = path_override();
   if (o == 1) return Path::kFused;
   if (o == 2) return Path::kSplit;
-  return g->batch_path == 2 ? Path::kSplit : Path::kFused;
+  if (g->batch_path != 0) return g->batch_path == 2 ? Path::kSplit : Path::kFused;
+  return fused_spills(g, precision) ? Path::kSplit : Path::kFused;
 }
 
 // Chunk length of the fused kernel for a single frame: enough items to give every resident
@@ -450,9 +459,9 @@ int project_grid(int device, int64_t N) {
 }  // namespace
 
 namespace fv {
-size_t batch_device_bytes(const fv_gmm* g, const int64_t* sizes, int B) {
+size_t batch_device_bytes(const fv_gmm* g, const int64_t* sizes, int B, int precision) {
   const Consts& c = g->c;
-  const bool split = choose_batch(g) == Path::kSplit;
+  const bool split = choose_batch(g, precision) == Path::kSplit;
   const int P = batch_chunk(g);
   int64_t rows = 0, items = 0, groups = 0;
   for (int b = 0; b < B; ++b) {
@@ -738,7 +747,7 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
   if (!ws) return FV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ws->mu);
 
-  const Path path = choose_single(gmm, N);
+  const Path path = choose_single(gmm, N, precision);
   const int slices = c.Kp / fv::kCompsPerWave;
   int P = fv::kTile;
   // the two-pass path's second pass: component-sliced workgroups up to 256 components (more
@@ -853,7 +862,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   if (rows > ((int64_t)1 << 40) / std::max(Din, c.D)) return FV_E_UNSUPPORTED;
 
   // Frame-relative chunking: frame b's chunk j covers its rows [j*P, (j+1)*P).
-  const Path path = choose_batch(gmm);
+  const Path path = choose_batch(gmm, precision);
   const int P = batch_chunk(gmm);
   std::vector<fv::Frame> frames((size_t)B);
   int64_t n_items64 = 0, n_groups64 = 0;

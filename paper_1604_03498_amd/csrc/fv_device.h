@@ -280,6 +280,9 @@ __device__ __forceinline__ void estep_f32(const float* __restrict__ xr, const fl
         hi[r] = a[r] + cval;
         lo[r] = 0.f;
       }
+      // the adds complete before the next chain starts (FP32 MFMAs do not overlap VALU anyway),
+      // so the chain sum and the logit never need registers at the same time
+      __builtin_amdgcn_sched_barrier(0);
     } else {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -334,6 +337,9 @@ __device__ __forceinline__ void estep_f32_lds(const float* __restrict__ xr,
         hi[r] = a[r] + cval;
         lo[r] = 0.f;
       }
+      // the adds complete before the next chain starts (FP32 MFMAs do not overlap VALU anyway),
+      // so the chain sum and the logit never need registers at the same time
+      __builtin_amdgcn_sched_barrier(0);
     } else {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {

@@ -126,7 +126,7 @@ int finalize_blocks(const Consts& c);
 
 // Device bytes one fv_encode_batch call needs for frames of the given sizes (workspace plus
 // device-resident X and out), used by the server's admission control.
-size_t batch_device_bytes(const struct ::fv_gmm* g, const int64_t* sizes, int B);
+size_t batch_device_bytes(const struct ::fv_gmm* g, const int64_t* sizes, int B, int precision);
 
 // ---- 16-bit operand forms (one translation unit per form) --------------------------------
 struct Frags16 {

@@ -148,7 +148,7 @@ size_t footprint(const fv_server* s, const std::vector<int64_t>& sizes) {
     for (int64_t r : sizes) n += (size_t)r * s->D * 4 + s->out_len * 4;
     return n;
   }
-  return fv::batch_device_bytes(s->gmm, sizes.data(), (int)sizes.size());
+  return fv::batch_device_bytes(s->gmm, sizes.data(), (int)sizes.size(), s->cfg.precision);
 }
 
 void finish_request(fv_server* s, Request* r, int status, double t) {
