@@ -132,3 +132,27 @@ def test_em_step_errors(fv):
         fv.em_step(h, np.zeros((0, 4), np.float32))
     with pytest.raises(fv.FvError):
         fv.em_step(h, np.zeros((5, 4), np.float32), var_floor=-1.0)
+
+
+def test_em_single_component_closed_form(fv):
+    """K = 1: every posterior is exactly 1, so the step returns w = 1, the sample mean and the
+    biased sample variance (numpy, float64), and the log-likelihood of a single Gaussian."""
+    say("[gpu] em K=1 closed form")
+    rng = np.random.default_rng(4)
+    D, N = 24, 5000
+    X = (rng.standard_normal((N, D)) * rng.uniform(0.5, 2.0, D) + rng.uniform(-1, 1, D)).astype(np.float32)
+    X64 = X.astype(np.float64)
+    mu0 = np.zeros((1, D), np.float32)
+    var0 = np.ones((1, D), np.float32)
+    h = fv.gmm_load(np.ones(1, np.float32), mu0, var0)
+    w, mu, var, ll = fv.em_step(h, X, var_floor=1e-6)
+    assert w[0] == 1.0
+    assert np.max(np.abs(mu[0] - X64.mean(axis=0)) / X64.std(axis=0)) < 1e-5
+    assert np.max(np.abs(var[0] / X64.var(axis=0) - 1.0)) < 1e-5
+    ll_ref = float(np.sum(-0.5 * (X64 ** 2).sum(axis=1) - 0.5 * D * np.log(2 * np.pi)))
+    assert abs(ll - ll_ref) < 1e-6 * abs(ll_ref)
+    # the variance floor binds for a constant feature
+    Xc = X.copy()
+    Xc[:, 3] = 0.25
+    _, _, varc, _ = fv.em_step(h, Xc, var_floor=1e-3)
+    assert varc[0, 3] == np.float32(1e-3)

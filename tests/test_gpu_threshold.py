@@ -197,3 +197,24 @@ def test_threshold_server(fv):
                 outs[t] = out
     for X, t in zip(frames, tickets):
         check_norm("server", outs[t], oracle.encode_gmm(X, g, tau=TAU), 1e-5)
+
+
+def test_threshold_single_component_and_tiny_frames(fv):
+    """K = 1 (every posterior is 1: the threshold removes nothing, so the result equals the
+    exact encode bitwise) and frames of 1 and 2 descriptors."""
+    import torch
+    say("[gpu] threshold K=1 and tiny frames")
+    g = fvsynth.gmm(1, 8, 5)
+    X = fvsynth.frame(g, 100, 6)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    for prec in (0, 1):
+        a = fv.encode(h, X, precision=prec)
+        b = fv.encode(h, X, precision=prec, flags=fv.THRESHOLD)
+        assert np.array_equal(a, b)
+    g = fvsynth.gmm(64, 32, 1)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    for n in (1, 2):
+        X = fvsynth.frame(g, n, 40 + n, 0.0)
+        ref = oracle.encode_gmm(X, g, tau=TAU)
+        got = fv.encode(h, torch.from_numpy(X).cuda(), flags=fv.THRESHOLD).cpu().numpy()
+        check_norm(f"n={n}", got, ref, 1e-5)
