@@ -22,8 +22,9 @@
  * the paper's mode: a term (t, k) then enters u, v (and the gamma sum inside v) only if
  * gamma_tk > FV_THRESHOLD_TAU (Algorithm 1's test), and groups of MFMA steps whose terms all
  * fall below it are skipped (the paper's early termination of Phase 2, Sec. 3.3).  A frame with
- * N = 0 encodes to 2KD zeros.  Non-finite descriptor values are not checked: NaN propagates to
- * the output.
+ * N = 0 encodes to 2KD zeros.  Non-finite descriptor values are not checked: a NaN makes every
+ * statistic of its frame NaN, so with FV_NO_POWER_NORM the vector is NaN, while the signed
+ * square root takes the sign of NaN as 0 and the normalised vector is then all zeros.
  *
  * Return codes: FV_OK (0), FV_PENDING (1), or a negative FV_E_* code; fv_strerror() names
  * them.  No C++ exception crosses this interface.  Functions are thread-safe unless stated.

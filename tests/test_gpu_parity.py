@@ -209,3 +209,46 @@ def test_max_sizes(fv, D):
     gotb = fv.encode_batch(h, torch.from_numpy(Xb).cuda(), off).cpu().numpy()
     for b in range(2):
         _check(f"K{K}_D{D}_batch{b}", gotb[b], refb[b])
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp32", "bf16_split", "fp16_split"])
+def test_runs_are_bitwise_reproducible(fv, prec, monkeypatch):
+    """Every sum has a fixed order: repeated encodes give the same bits on both single-frame
+    paths, in threshold mode and for a batch."""
+    import torch
+    say(f"[gpu] reproducibility prec={prec}")
+    g = fvsynth.gmm(256, 64, 0)
+    h = _gmm(fv, g)
+    X = torch.from_numpy(fvsynth.frame(g, 8000, 100, 0.05)).cuda()
+    for p in ("fused", "split"):
+        monkeypatch.setenv("FV_PATH", p)
+        for fl in (0, fv.THRESHOLD):
+            runs = [fv.encode(h, X, precision=prec, flags=fl).cpu().numpy() for _ in range(3)]
+            assert all(np.array_equal(runs[0], r) for r in runs[1:]), (p, fl)
+    monkeypatch.delenv("FV_PATH")
+    Xb, off = fvsynth.batch_frames(g, [3000, 1, 5000], seed0=11)
+    Xbd = torch.from_numpy(Xb).cuda()
+    runs = [fv.encode_batch(h, Xbd, off, precision=prec).cpu().numpy() for _ in range(3)]
+    assert all(np.array_equal(runs[0], r) for r in runs[1:])
+
+
+def test_non_finite_descriptor_propagates(fv):
+    """Non-finite descriptors are not checked (documented): one NaN makes every statistic of its
+    frame NaN, so the raw vector is NaN; the signed square root takes the sign of NaN as 0, so
+    the normalised vector is all zeros, as in the oracle.  The other frames of a batch are
+    unaffected."""
+    say("[gpu] NaN propagation")
+    g = fvsynth.gmm(16, 8, 0)
+    h = _gmm(fv, g)
+    X = fvsynth.frame(g, 300, 3, 0.0)
+    Xn = X.copy()
+    Xn[17, 2] = np.nan
+    raw = fv.encode(h, Xn, flags=fv.NO_POWER_NORM | fv.NO_L2_NORM)
+    assert np.all(np.isnan(raw))
+    out = fv.encode(h, Xn)
+    assert np.all(out == 0)
+    assert np.all(oracle.encode_gmm(Xn, g) == 0)
+    Xb = np.concatenate([X, Xn])
+    outb = fv.encode_batch(h, Xb, np.array([0, 300, 600], np.int64))
+    assert np.array_equal(outb[0], fv.encode_batch(h, X, np.array([0, 300], np.int64))[0])
+    assert np.all(np.isfinite(outb[0])) and np.all(outb[1] == 0)
