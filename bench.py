@@ -414,7 +414,14 @@ def cpu_baseline(g, frames, seconds):
         done += int(o[-1])
         n_frames += len(idx)
     dt = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": done / dt, "unit": "descriptors/s", "cores": nthreads, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"{n_frames} encodes of the workload frame ({done} descriptors) in "
                       f"{dt:.1f} s; FP64 C oracle, whole frames spread over {nthreads} threads"}
 
@@ -454,8 +461,28 @@ def main():
              "roofline": roofline(form, K, D, N, st_avg, path),
              "finalize_avg_us": round(fi_avg * 1e3, 3), "launches": st_n}
         if lat.size:
-            r["latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+            r["latency_ms"] = {"p10": float(np.percentile(lat, 10)),
+                               "p50": float(np.percentile(lat, 50)),
+                               "p90": float(np.percentile(lat, 90)),
+                               "p99": float(np.percentile(lat, 99)),
                                "max": float(lat.max()), "samples": int(lat.size)}
+        # end to end from host memory: X in pinned host memory, the output back in host memory
+        # (the H2D and D2H copies inside each call)
+        if a.latency_samples:
+            Xh = torch.from_numpy(X).pin_memory()
+            outh = torch.empty(2 * K * D, dtype=torch.float32).pin_memory()
+            for _ in range(5):
+                fv.encode(h, Xh, out=outh, precision=PREC_CODE[form], stream=stream)
+            hl = []
+            for _ in range(min(100, a.latency_samples)):
+                t0h = time.perf_counter()
+                fv.encode(h, Xh, out=outh, precision=PREC_CODE[form], stream=stream)
+                hl.append((time.perf_counter() - t0h) * 1e3)
+            hl = np.array(hl)
+            r["host_input_end_to_end"] = {
+                "value": N / (np.median(hl) * 1e-3), "p50_ms": float(np.median(hl)),
+                "p90_ms": float(np.percentile(hl, 90)), "samples": int(hl.size),
+                "note": "pinned host X and output; H2D, encode and D2H in each synchronous call"}
         results[form] = r
         outputs[form] = out.cpu().numpy()
         log(f"[bench]   {r['value']:.4e} desc/s, {r['ms_per_step']:.4f} ms/step, "
@@ -699,8 +726,10 @@ def main():
         from oracle.metrics import errors
         result["oracle_c1"] = oracle_c1()
         ref = oracle.encode_gmm(X, g)
+        from oracle.metrics import per_block
         for f in forms:
             result["forms"][f]["error_vs_oracle"] = errors(outputs[f], ref)
+            result["forms"][f]["error_per_block"] = per_block(outputs[f], ref, K, D, worst=10)
         if paper:
             ref_t = oracle.encode_gmm(X, g, tau=fv.THRESHOLD_TAU)
             ref_tc = oracle.encode_gmm(Xc, g, tau=fv.THRESHOLD_TAU)
