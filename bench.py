@@ -432,8 +432,8 @@ def main():
         pmc_summary(a.pmc_summary[0], a.pmc_summary[1], a.calib_copy_mb or 256)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "single-GPU build: run with --gpus 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "one GPU only: run with --gpus 1 (frames would shard across "
+                                   "GPUs with only the results gathered; not built)"}))
         sys.exit(2)
     import torch
     import fvsynth
