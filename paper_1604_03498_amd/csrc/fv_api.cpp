@@ -321,11 +321,12 @@ int path_override() {
 // one 8-wave workgroup per CU at 256 components (register bound), more for fewer waves.
 int resident_fused(int device, int Wg) { return device_cu_count(device) * std::max(1, 8 / Wg); }
 
-// Above DP = 80 the 8-wave FP32 fused kernel spills registers and the two-pass path (whose
-// group-wise second pass runs 4 waves there) is faster: 1.45 against 1.85 ms for 32 frames at
-// K = 256, D = 96.  The 16-bit forms and smaller D keep the fused kernel.
+// Above DP = 64 the 8-wave FP32 fused kernel spills registers, and the two-pass path (whose
+// group-wise second pass runs 4 waves there) is as fast or faster: 32 frames at K = 256 took
+// 1.14 against 1.15 ms at D = 80 and 1.45 against 1.85 ms at D = 96.  The 16-bit forms keep
+// the fused kernel (0.35 against 0.45 ms at D = 80).
 bool fused_spills(const fv_gmm* g, int precision) {
-  return precision == FV_PREC_FP32 && g->c.DP > 80 && g->c.Wg == fv::kMaxWaves;
+  return precision == FV_PREC_FP32 && g->c.DP > 64 && g->c.Wg == fv::kMaxWaves;
 }
 
 // Single frame: the fused kernel needs several 32-row tiles per resident workgroup to amortise
