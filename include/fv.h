@@ -56,6 +56,14 @@ extern "C" {
 #define FV_PREC_BF16_SPLIT 1  /* bf16 hi/lo operands, 3 products (hi*hi + hi*lo + lo*hi) */
 #define FV_PREC_FP16_SPLIT 2  /* fp16 hi/lo operands, 3 products */
 #define FV_PREC_BF16 3        /* plain bf16 operands (accuracy control only) */
+/*
+ * Range of the fp16 split: the operand entries mu/sigma^2 and 1/(2 sigma^2) (times log2 e)
+ * and the descriptor values x and x^2 are rounded to fp16, whose largest finite value is
+ * 65504.  A model with an entry beyond it (a variance below about 1.1e-5, or a large
+ * |mu|/sigma^2) is refused for this form with FV_E_UNSUPPORTED; descriptors need |x| < 255.9,
+ * else the result is not finite.  Entries below 2^-14 lose relative precision (fp16
+ * subnormals).  The bf16 forms have the FP32 exponent range.
+ */
 
 /* ---- flags ----------------------------------------------------------------------------- */
 #define FV_X_DEVICE 1u        /* X (and offsets' rows) live in device memory; else host memory */
@@ -105,8 +113,8 @@ int fv_gmm_info(const fv_gmm* gmm, int* K, int* D, int* device);
  *   hip_stream a hipStream_t (NULL = the default stream) on the handle's device.
  * The caller owns X and out.  N = 0 writes zeros.  Device X must be 4-byte aligned; a
  * 16-byte aligned X with D % 4 == 0 takes the vector-load path.
- * Errors: FV_E_INVAL (null pointers, N < 0, bad precision or flags), FV_E_NOMEM,
- * FV_E_DEVICE.
+ * Errors: FV_E_INVAL (null pointers, N < 0, bad precision or flags), FV_E_UNSUPPORTED (the
+ * fp16 split for a model outside its range, see above), FV_E_NOMEM, FV_E_DEVICE.
  */
 int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int precision,
               unsigned flags, void* hip_stream);
@@ -205,7 +213,8 @@ int fv_encode_batch_projected(const fv_gmm* gmm, const fv_pca* pca, const float*
  * X [N x D] float32 row-major, host or device (FV_X_DEVICE; no other flag).  Outputs are host
  * arrays: weights [K], means [K x D], variances [K x D] (float32), *loglik (double).  Returns
  * after the stream has finished.  Errors: FV_E_INVAL (null pointers, N < 1, bad precision,
- * flags, negative or non-finite var_floor), FV_E_NOMEM, FV_E_DEVICE.
+ * flags, negative or non-finite var_floor), FV_E_UNSUPPORTED (the fp16 split out of range),
+ * FV_E_NOMEM, FV_E_DEVICE.
  */
 int fv_em_step(const fv_gmm* gmm, const float* X, int64_t N, int precision, float var_floor,
                unsigned flags, void* hip_stream, float* weights, float* means, float* variances,
@@ -266,7 +275,8 @@ typedef struct fv_server_stats {
 void fv_server_config_default(fv_server_config* cfg);
 
 /* Create a server for `gmm` (may be NULL only with FV_EXEC_FAKE).  The handle must outlive the
- * server.  Errors: FV_E_INVAL, FV_E_NOMEM, FV_E_DEVICE. */
+ * server.  Errors: FV_E_INVAL, FV_E_UNSUPPORTED (the fp16 split out of range), FV_E_NOMEM,
+ * FV_E_DEVICE. */
 int fv_server_create(const fv_gmm* gmm, const fv_server_config* cfg, fv_server** out);
 
 /* Stop the scheduler (waits for in-flight launches) and free everything; unpolled results are
@@ -275,7 +285,8 @@ int fv_server_destroy(fv_server* srv);
 
 /* Enqueue one frame X [N x D] (host memory; copied before return, so the caller may reuse X).
  * Thread-safe and non-blocking.  Returns FV_OK and a ticket, FV_E_BUDGET if the frame can never
- * fit the budget, FV_E_AGAIN if the queue is full, FV_E_INVAL for bad arguments. */
+ * fit the budget, FV_E_AGAIN if the queue is full, FV_E_UNSUPPORTED for N above the encoder's
+ * row limit (2^40 / D), FV_E_INVAL for bad arguments. */
 int fv_server_submit(fv_server* srv, const float* X, int64_t N, uint64_t* ticket);
 
 /* As fv_server_submit for a frame already in device memory: X [N x D] f32 row-major on the
@@ -301,6 +312,17 @@ const char* fv_strerror(int code);
 
 /* The last HIP error code seen by the calling thread inside libfv (0 if none). */
 int fv_last_device_error(void);
+
+/*
+ * Release what the library caches for one (device, stream) pair: device scratch (partial
+ * statistics, normalisers, staging), pinned host staging and captured graphs, all created on
+ * first use of that stream and otherwise kept for the life of the process.  Call it before
+ * destroying a stream that was passed to fv_encode* / fv_em_step; it waits for the stream,
+ * and no call on that stream may be in flight or start concurrently.  A pair never used is a
+ * no-op; later calls on the stream allocate again.  Servers release their own streams in
+ * fv_server_destroy.  Errors: FV_E_DEVICE (the stream, a free, or the device failed).
+ */
+int fv_stream_release(int device, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -21,6 +22,9 @@
 namespace {
 
 thread_local int t_last_hip_error = 0;
+
+// Serial numbers of loaded handles, starting at 1 (0 means "no handle" in a graph key).
+std::atomic<uint64_t> g_next_serial{1};
 
 constexpr unsigned kAllFlags =
     FV_X_DEVICE | FV_OUT_DEVICE | FV_NO_POWER_NORM | FV_NO_L2_NORM | FV_ASYNC | FV_THRESHOLD;
@@ -81,9 +85,11 @@ int device_cu_count(int device) {
 // stream).  Work on one stream is ordered, so reusing the buffers between calls is safe; a
 // buffer is only replaced after the stream has drained.
 // Everything a captured launch sequence bakes in: a replay is valid only for an equal key.
+// Handles enter by serial number, not address: a handle loaded after another was freed may
+// reuse its address, and a graph holds the old handle's device pointers.
 struct GraphKey {
   int kind = 0;  // 0 = fv_encode, 1 = fv_encode_batch
-  const fv_gmm* gmm = nullptr;
+  uint64_t gmm = 0;
   int precision = 0;
   unsigned flags = 0;
   int path = 0, P = 0;
@@ -93,7 +99,7 @@ struct GraphKey {
   const void* out = nullptr;
   const void* dev = nullptr;
   const void* pinned = nullptr;
-  const fv_pca* pca = nullptr;
+  uint64_t pca = 0;  // 0: no projection
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && gmm == o.gmm && precision == o.precision && flags == o.flags &&
            path == o.path && P == o.P && rows == o.rows && B == o.B && n_items == o.n_items &&
@@ -545,6 +551,31 @@ const char* fv_strerror(int code) {
 
 int fv_last_device_error(void) { return t_last_hip_error; }
 
+int fv_stream_release(int device, void* hip_stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  std::unique_ptr<Workspace> ws;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({device, s});
+    if (it == g_ws.end()) return FV_OK;
+    ws = std::move(it->second);
+    g_ws.erase(it);
+  }
+  if (!ws) return FV_OK;
+  DeviceGuard g(device);
+  if (g.status() != hipSuccess) return hip_fail(g.status());
+  std::lock_guard<std::mutex> lk(ws->mu);
+  int rc = FV_OK;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) rc = hip_fail(e);
+  drop_graphs(ws.get());
+  if (ws->dev && (e = hipFree(ws->dev)) != hipSuccess) rc = hip_fail(e);
+  if (ws->pinned && (e = hipHostFree(ws->pinned)) != hipSuccess) rc = hip_fail(e);
+  if (ws->pin_done) (void)hipEventDestroy(ws->pin_done);
+  ws->dev = ws->pinned = nullptr;
+  return rc;
+}
+
 int fv_gmm_load(int K, int D, const float* priors, const float* means, const float* variances,
                 int device, fv_gmm** out) {
   if (!out) return FV_E_INVAL;
@@ -584,6 +615,7 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
   std::vector<float> A((size_t)2 * DP * Kp, 0.f), cc((size_t)Kp, -1e30f);
   const size_t nfrag = (size_t)2 * DP * Kp;  // same element count as A, fragment order
   std::vector<uint16_t> abh(nfrag, 0), abl(nfrag, 0), ahh(nfrag, 0), ahl(nfrag, 0);
+  bool f16_fits = true;
   std::vector<double> mu64(KD), isd64(KD), ivar64(KD), cu64(K), cv64(K);
   for (int k = 0; k < K; ++k) {
     double logdet = 0.0, quad = 0.0;
@@ -616,6 +648,7 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
           abh[o] = bh;
           abl[o] = bf16_rne(v - bf16_to_f32(bh));
           const _Float16 fh = (_Float16)v;
+          f16_fits = f16_fits && std::isfinite((float)fh);
           ahh[o] = f16_bits(fh);
           ahl[o] = f16_bits((_Float16)(v - (float)fh));
         }
@@ -680,6 +713,8 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
   h->K = K;
   h->D = D;
   h->device = device;
+  h->serial = g_next_serial.fetch_add(1);
+  h->f16_fits = f16_fits;
   h->c = c;
   h->dev_block = blk;
   *out = h.release();
@@ -737,7 +772,7 @@ int fv_gmm_info(const fv_gmm* gmm, int* K, int* D, int* device) {
 static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int64_t N,
                        float* out, int precision, unsigned flags, void* hip_stream) {
   if (!gmm || !out || N < 0 || (N > 0 && !X)) return FV_E_INVAL;
-  if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
+  if (const int fs = fv_form_status(gmm, precision)) return fs;
   if (flags & ~kAllFlags) return FV_E_INVAL;
   if (pca && (pca->D != gmm->D || pca->device != gmm->device)) return FV_E_INVAL;
   const fv::Consts c = call_consts(gmm, flags);
@@ -825,7 +860,7 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
                          (flags & FV_OUT_DEVICE) && !timing_enabled();
   GraphKey key;
   key.kind = 0;
-  key.gmm = gmm;
+  key.gmm = gmm->serial;
   key.precision = precision;
   key.flags = flags & kGraphFlags;
   key.path = (int)path;
@@ -836,7 +871,7 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
   key.X = Xd;
   key.out = Od;
   key.dev = ws->dev;
-  key.pca = pca;
+  key.pca = pca ? pca->serial : 0;
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   if (!(flags & FV_OUT_DEVICE))
@@ -850,7 +885,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
                              const int64_t* offsets, int B, float* out, int precision,
                              unsigned flags, void* hip_stream) {
   if (!gmm || !offsets || B < 0 || (B > 0 && !out)) return FV_E_INVAL;
-  if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
+  if (const int fs = fv_form_status(gmm, precision)) return fs;
   if (flags & ~kAllFlags) return FV_E_INVAL;
   if (pca && (pca->D != gmm->D || pca->device != gmm->device)) return FV_E_INVAL;
   if (offsets[0] != 0) return FV_E_INVAL;
@@ -979,7 +1014,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
                          (flags & FV_OUT_DEVICE) && !timing_enabled();
   GraphKey key;
   key.kind = 1;
-  key.gmm = gmm;
+  key.gmm = gmm->serial;
   key.precision = precision;
   key.flags = flags & kGraphFlags;
   key.path = (int)path;
@@ -992,7 +1027,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   key.out = Od;
   key.dev = ws->dev;
   key.pinned = ws->pinned;
-  key.pca = pca;
+  key.pca = pca ? pca->serial : 0;
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   FV_HIP(hipEventRecord(ws->pin_done, s));
@@ -1074,6 +1109,7 @@ int fv_pca_load(int Din, int D, const float* A, const float* mean, int device, f
   h->Din = Din;
   h->D = D;
   h->device = device;
+  h->serial = g_next_serial.fetch_add(1);
   h->p = p;
   h->dev_block = blk;
   *out = h.release();
@@ -1140,7 +1176,7 @@ int fv_em_step(const fv_gmm* gmm, const float* X, int64_t N, int precision, floa
                unsigned flags, void* hip_stream, float* weights, float* means, float* variances,
                double* loglik) {
   if (!gmm || N < 1 || !X || !weights || !means || !variances || !loglik) return FV_E_INVAL;
-  if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
+  if (const int fs = fv_form_status(gmm, precision)) return fs;
   if (flags & ~(unsigned)FV_X_DEVICE) return FV_E_INVAL;
   if (!(var_floor >= 0.f) || !finite_f(var_floor)) return FV_E_INVAL;
   const fv::Consts c = call_consts(gmm, 0);

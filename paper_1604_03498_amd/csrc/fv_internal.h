@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fv.h"
+
 struct fv_gmm;
 
 namespace fv {
@@ -179,6 +181,7 @@ hipError_t launch_em(const Consts& c, const float* partials, int n_items, int64_
 
 struct fv_pca {
   int Din = 0, D = 0, device = 0;
+  uint64_t serial = 0;  // unique per load in the process (a freed handle's address can recur)
   fv::ProjConsts p{};
   void* dev_block = nullptr;
 };
@@ -186,10 +189,20 @@ struct fv_pca {
 // The public handle (opaque in the C ABI).
 struct fv_gmm {
   int K = 0, D = 0, device = 0;
+  uint64_t serial = 0;  // unique per load in the process (a freed handle's address can recur)
   fv::Consts c{};
   void* dev_block = nullptr;  // one allocation holding every constant array
+  bool f16_fits = true;       // every fp16 operand fragment is finite (else no fp16 form)
   // launch tuning (0 = automatic)
   int batch_chunk = 0;
   int batch_path = 0;
   int64_t single_split_below = 0;
 };
+
+// Status of an arithmetic form for this model: FV_OK, FV_E_INVAL for an unknown form, or
+// FV_E_UNSUPPORTED for the fp16 split when the model's operand entries overflow fp16.
+inline int fv_form_status(const fv_gmm* g, int precision) {
+  if (precision < FV_PREC_FP32 || precision > FV_PREC_BF16) return FV_E_INVAL;
+  if (precision == FV_PREC_FP16_SPLIT && g != nullptr && !g->f16_fits) return FV_E_UNSUPPORTED;
+  return FV_OK;
+}

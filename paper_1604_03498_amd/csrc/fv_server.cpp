@@ -43,6 +43,8 @@ class HostPool {
       for (void* p : kv.second) release(p);
   }
   void* get(size_t bytes, size_t* cls_out) {
+    *cls_out = 0;
+    if (bytes > ((size_t)1 << 46)) return nullptr;  // beyond any frame the encoder accepts
     size_t cls = 1u << 16;
     while (cls < bytes) cls <<= 1;
     *cls_out = cls;
@@ -367,7 +369,7 @@ int fv_server_create(const fv_gmm* gmm, const fv_server_config* cfg, fv_server**
   *out = nullptr;
   fv_server_config c = *cfg;
   if (c.executor != FV_EXEC_HIP && c.executor != FV_EXEC_FAKE) return FV_E_INVAL;
-  if (c.precision < FV_PREC_FP32 || c.precision > FV_PREC_BF16) return FV_E_INVAL;
+  if (const int fs = fv_form_status(gmm, c.precision)) return fs;
   if (c.flags & ~(FV_NO_POWER_NORM | FV_NO_L2_NORM | FV_THRESHOLD)) return FV_E_INVAL;
   if (c.executor == FV_EXEC_HIP && !gmm) return FV_E_INVAL;
   if (!gmm && (c.fake_K < 1 || c.fake_D < 1)) return FV_E_INVAL;
@@ -428,6 +430,8 @@ int fv_server_destroy(fv_server* s) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->gmm->device);
     for (Lane& L : s->lanes) {
+      // the encoder's cached buffers and graphs for this lane's stream
+      if (L.stream && fv_stream_release(s->gmm->device, L.stream) != FV_OK) rc = FV_E_DEVICE;
       if (L.dX && hipFree(L.dX) != hipSuccess) rc = FV_E_DEVICE;
       if (L.dOut && hipFree(L.dOut) != hipSuccess) rc = FV_E_DEVICE;
       if (L.done) (void)hipEventDestroy(L.done);
@@ -443,6 +447,7 @@ namespace {
 
 int submit_impl(fv_server* s, const float* X, int64_t N, uint64_t* ticket, bool device) {
   if (!s || !ticket || N < 0 || (N > 0 && !X)) return FV_E_INVAL;
+  if (N > ((int64_t)1 << 40) / s->D) return FV_E_UNSUPPORTED;  // the encoder's row limit
   const std::vector<int64_t> one{N};
   if (s->cfg.hbm_budget_bytes > 0 && footprint(s, one) > s->cfg.hbm_budget_bytes) {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -25,7 +25,8 @@ EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "f
                     "fv_server_next_done",
                     "fv_server_get_stats", "fv_strerror", "fv_last_device_error",
                     "fv_pca_load", "fv_pca_free", "fv_pca_info", "fv_project",
-                    "fv_encode_projected", "fv_encode_batch_projected", "fv_em_step")
+                    "fv_encode_projected", "fv_encode_batch_projected", "fv_em_step",
+                    "fv_stream_release")
 EXEC_HIP, EXEC_FAKE = 0, 1
 
 
@@ -123,8 +124,10 @@ def load():
     lib.fv_last_device_error.argtypes = []
     lib.fv_em_step.argtypes = [vp, vp, i64, i32, ctypes.c_float, u32, vp, vp, vp, vp,
                                ctypes.POINTER(ctypes.c_double)]
+    lib.fv_stream_release.argtypes = [i32, vp]
     for f in (lib.fv_pca_load, lib.fv_pca_free, lib.fv_pca_info, lib.fv_project,
-              lib.fv_encode_projected, lib.fv_encode_batch_projected, lib.fv_em_step):
+              lib.fv_encode_projected, lib.fv_encode_batch_projected, lib.fv_em_step,
+              lib.fv_stream_release):
         f.restype = i32
     for f in (lib.fv_gmm_load, lib.fv_gmm_free, lib.fv_gmm_info, lib.fv_encode,
               lib.fv_encode_batch, lib.fv_kernel_timing, lib.fv_kernel_timing_read,
@@ -246,6 +249,13 @@ def _stream_handle(stream, device: int):
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def stream_release(stream, device: int = 0) -> None:
+    """fv_stream_release: free the library's cached scratch, staging and graphs for `stream`
+    (a torch stream or a raw hipStream_t) on `device`; call before the stream is destroyed."""
+    _check(load().fv_stream_release(device, ctypes.c_void_p(_stream_handle(stream, device))),
+           "fv_stream_release")
 
 
 def _marshal_x(g, X, width: int | None = None):

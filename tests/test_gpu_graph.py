@@ -77,6 +77,47 @@ def test_batch_replays_with_new_table(fv, monkeypatch):
             assert np.array_equal(out.cpu().numpy(), direct[i]), (rep, i)
 
 
+def test_reloaded_models_do_not_replay_stale_graphs(fv, monkeypatch):
+    """Captured sequences are keyed by the handle's load serial, not its address: a model
+    loaded after another was freed (its handle may land at the freed address, its constants
+    elsewhere) is encoded with its own constants.  Each reload cycle's graph result must equal
+    the direct encode with that model; the same holds for projection handles."""
+    import torch
+    say("[gpu] graph cache across free and reload")
+    stream = torch.cuda.Stream()
+    X = fvsynth.frame(fvsynth.gmm(256, 64, 0), 8000, 100, 0.05)
+    Xd = torch.from_numpy(X).cuda()
+    out = torch.empty(2 * 256 * 64, device="cuda")
+    addrs = set()
+    for cycle in range(4):
+        g = fvsynth.gmm(256, 64, 20 + cycle)
+        h = fv.gmm_load(g.weights, g.means, g.variances)
+        addrs.add(h.handle)
+        monkeypatch.setenv("FV_GRAPH", "0")
+        ref = fv.encode(h, Xd, out=out.clone(), stream=stream).cpu().numpy()
+        monkeypatch.setenv("FV_GRAPH", "1")
+        for _ in range(2):
+            fv.encode(h, Xd, out=out, flags=fv.ASYNC, stream=stream)
+            stream.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), cycle
+        h.free()
+    say(f"  distinct handle addresses over 4 loads: {len(addrs)}")
+    g = fvsynth.gmm(256, 64, 0)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    R = torch.from_numpy(fvsynth.raw_frame(g, fvsynth.pca(64, 0), 4000, 5, 0.05)).cuda()
+    for cycle in range(3):
+        p = fvsynth.pca(64, cycle)
+        hp = fv.pca_load(p.A, p.mean)
+        monkeypatch.setenv("FV_GRAPH", "0")
+        ref = fv.encode_projected(h, hp, R, out=out.clone(), stream=stream).cpu().numpy()
+        monkeypatch.setenv("FV_GRAPH", "1")
+        for _ in range(2):
+            fv.encode_projected(h, hp, R, out=out, flags=fv.ASYNC, stream=stream)
+            stream.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), ("pca", cycle)
+        hp.free()
+
+
 def test_autotuner_keeps_results_within_tolerance(fv, tmp_path, monkeypatch):
     import torch
     import oracle

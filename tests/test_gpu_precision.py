@@ -3,6 +3,7 @@ the plain-bf16 control, through the C ABI, against the FP64 oracle.
 
 Gate: E_inf <= 1e-3 and E_2 <= 1e-3 for BF16_SPLIT and FP16_SPLIT; the plain-bf16 form is a
 control that must stay finite and be clearly less accurate than the split form."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -107,3 +108,36 @@ def test_bf16_split_large_k(fv):
     e = errors(got, ref)
     say(f"  {e}")
     assert e["e_inf"] <= TOL_SPLIT and e["e_2"] <= TOL_SPLIT
+
+
+def test_fp16_split_refuses_models_beyond_fp16_range(fv):
+    """A variance of 1e-6 puts 1/(2 sigma^2) log2 e = 7.2e5 into the E-step operand, beyond
+    fp16's largest finite value: the fp16 split is refused (FV_E_UNSUPPORTED) by the encoder,
+    the batch, the EM step and the server, and a model inside the range is not."""
+    import torch
+    say("[gpu] fp16 split range check")
+    g = fvsynth.gmm(64, 16, 3)
+    var = g.variances.copy()
+    var[5, 3] = 1e-6
+    g = dataclasses.replace(g, variances=var)
+    X = fvsynth.frame(g, 3000, 4, 0.0)
+    h = fv.gmm_load(g.weights, g.means, var)
+    Xd = torch.from_numpy(X).cuda()
+    for call in (lambda: fv.encode(h, Xd, precision=2),
+                 lambda: fv.encode_batch(h, Xd, np.array([0, 1000, 3000], np.int64), precision=2),
+                 lambda: fv.em_step(h, X, precision=2)):
+        with pytest.raises(fv.FvError) as ei:
+            call()
+        assert ei.value.code == fv.E_UNSUPPORTED
+    with pytest.raises(fv.FvError) as ei:
+        fv.Server(h, fv.server_config(precision=2))
+    assert ei.value.code == fv.E_UNSUPPORTED
+    # FP32 and the bf16 split keep the FP32 exponent range: finite, unit-norm vectors (their
+    # accuracy on so stiff a model -- sigma = 1e-3 in one coordinate -- is not gated here)
+    for prec in (0, 1):
+        got = fv.encode(h, Xd, precision=prec).cpu().numpy().astype(np.float64)
+        say(f"  precision {prec}: E_inf vs oracle {errors(got, oracle.encode_gmm(X, g))['e_inf']:.2e}")
+        assert np.all(np.isfinite(got)) and abs(np.linalg.norm(got) - 1.0) < 1e-5
+    # a model inside the range still takes the fp16 split
+    h2 = fv.gmm_load(g.weights, g.means, np.maximum(var, 0.5).astype(np.float32))
+    assert np.all(np.isfinite(fv.encode(h2, Xd, precision=2).cpu().numpy()))

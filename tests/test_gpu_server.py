@@ -137,3 +137,54 @@ def test_device_submission_matches_host_submission(fv):
         e = errors(out, oracle.encode_gmm(frames[i], g))
         say(f"  frame {i} N={sizes[i]} e_inf={e['e_inf']:.2e}")
         assert e["e_inf"] <= 1e-3 and e["e_2"] <= 1e-3
+
+
+def test_stream_release_and_server_cycles(fv):
+    """fv_stream_release frees a stream's cached scratch, staging and graphs: device memory
+    comes back, and the next encode on that stream allocates and captures again with the same
+    bits.  Servers release their lane streams on destroy: repeated create / encode / destroy
+    cycles give the same results and do not accumulate device memory."""
+    import torch
+    say("[gpu] stream release and server cycles")
+    g = fvsynth.gmm(512, 80, 0)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    frames = [fvsynth.frame(g, n, 70 + i, 0.05) for i, n in enumerate((32000, 32000, 8000))]
+    X, off = np.concatenate(frames), np.cumsum([0, 32000, 32000, 8000])
+    Xd = torch.from_numpy(X).cuda()
+    out = torch.empty(3, 2 * 512 * 80, device="cuda")
+    st = torch.cuda.Stream()
+    fv.stream_release(st)                                   # never used: nothing to do
+    fv.encode_batch(h, Xd, off, out=out, precision=1, flags=fv.ASYNC, stream=st)
+    st.synchronize()
+    first = out.cpu().numpy()
+    torch.cuda.synchronize()
+    before = torch.cuda.mem_get_info()[0]
+    fv.stream_release(st)
+    after = torch.cuda.mem_get_info()[0]
+    say(f"  released {(after - before) / 2**20:.1f} MiB")
+    assert after - before >= 16 << 20                      # partial slots alone are ~21 MiB
+    out.zero_()
+    torch.cuda.synchronize()
+    fv.encode_batch(h, Xd, off, out=out, precision=1, flags=fv.ASYNC, stream=st)
+    st.synchronize()
+    assert np.array_equal(out.cpu().numpy(), first)
+    fv.stream_release(st)
+
+    def cycle():
+        with fv.Server(h, fv.server_config(precision=fv.PREC_BF16_SPLIT, n_streams=2,
+                                           max_batch_frames=1)) as s:
+            ts = [s.submit(F) for F in frames]
+            res = drain(s, ts)
+        return [res[t][1] for t in ts]
+
+    ref = cycle()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for c in range(4):
+        got = cycle()
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), c
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    say(f"  free device memory change over 4 server cycles: {(free1 - free0) / 2**20:.1f} MiB")
+    assert free0 - free1 < 16 << 20

@@ -132,6 +132,23 @@ def test_empty_frame_and_invalid_arguments():
         fv.Server(None, fv.server_config(executor=fv.EXEC_FAKE, fake_K=1, fake_D=1, precision=9))
 
 
+def test_oversized_frame_is_refused_without_a_budget():
+    """With an unlimited budget a frame past the encoder's row limit (2^40 / D rows) is refused
+    with FV_E_UNSUPPORTED before anything is read or allocated (the staging size would
+    overflow)."""
+    import ctypes
+    lib = fv.load()
+    buf = np.zeros((1, D), np.float32)
+    with fake(hbm_budget_bytes=0) as s:
+        tk = ctypes.c_uint64()
+        for n in ((1 << 40) // D + 1, 1 << 62):
+            rc = lib.fv_server_submit(ctypes.c_void_p(s.handle), buf.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.c_int64(n), ctypes.byref(tk))
+            assert rc == fv.E_UNSUPPORTED
+        t = s.submit(np.ones((10, D), np.float32))        # the server still works
+        assert drain(s, [t])[t][0] == fv.OK
+
+
 def test_destroy_with_work_outstanding():
     s = fake(n_streams=1, fake_us_per_krow=10000.0)
     for _ in range(5):
