@@ -269,6 +269,7 @@ typedef struct fv_server_stats {
   size_t admitted_bytes, peak_admitted_bytes;
   double p50_ms, p99_ms, max_ms;  /* submit-to-done latency of completed requests */
   double busy_s;                  /* wall time with at least one launch in flight */
+  int64_t cancelled;              /* requests withdrawn by fv_server_cancel */
 } fv_server_stats;
 
 /* Fill a config with the defaults above (budget unlimited, FP32, HIP executor). */
@@ -299,6 +300,14 @@ int fv_server_submit_device(fv_server* srv, const float* X, int64_t N, uint64_t*
  * may be NULL) and st (may be NULL) filled -- the ticket is then consumed; a failure code
  * (FV_E_TIMEOUT, FV_E_DEVICE) also consumes it; FV_E_NOTFOUND for an unknown ticket. */
 int fv_server_poll(fv_server* srv, uint64_t ticket, float* out, fv_req_stats* st);
+
+/* Withdraw a request.  FV_OK: it was still queued (not yet admitted to a launch), or it had
+ * finished and was not yet polled; it is removed with its staging and result, the ticket is
+ * consumed and is never reported by fv_server_next_done.  FV_PENDING: it is already in a
+ * launch, which cannot be stopped; it finishes and is polled as usual.  FV_E_NOTFOUND for an
+ * unknown or consumed ticket.  A device frame (fv_server_submit_device) is no longer read once
+ * FV_OK is returned.  Thread-safe. */
+int fv_server_cancel(fv_server* srv, uint64_t ticket);
 
 /* Wait up to timeout_ms (< 0: forever) for any request to finish and return its ticket
  * (each finished ticket is reported once).  FV_PENDING on timeout. */

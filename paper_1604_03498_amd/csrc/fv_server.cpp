@@ -132,6 +132,7 @@ struct fv_server {
 
   // counters
   int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, launches = 0, rows_done = 0;
+  int64_t cancelled = 0;
   size_t admitted = 0, peak_admitted = 0;
   std::vector<double> lat_ms;
   double busy_s = 0, busy_since = -1;
@@ -525,6 +526,31 @@ int fv_server_poll(fv_server* s, uint64_t ticket, float* out, fv_req_stats* st) 
   return rc;
 }
 
+int fv_server_cancel(fv_server* s, uint64_t ticket) {
+  if (!s) return FV_E_INVAL;
+  Request* r = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->table.find(ticket);
+    if (it == s->table.end()) return FV_E_NOTFOUND;
+    r = it->second;
+    if (r->status == FV_PENDING) {
+      // still waiting for admission?  (admitted requests have left the queue)
+      auto q = std::find(s->queue.begin(), s->queue.end(), r);
+      if (q == s->queue.end()) return FV_PENDING;
+      s->queue.erase(q);
+    } else {
+      // finished, not polled: drop its completion notice
+      auto f = std::find(s->finished.begin(), s->finished.end(), ticket);
+      if (f != s->finished.end()) s->finished.erase(f);
+    }
+    s->table.erase(it);
+    ++s->cancelled;
+  }
+  free_request(s, r);
+  return FV_OK;
+}
+
 int fv_server_next_done(fv_server* s, double timeout_ms, uint64_t* ticket) {
   if (!s || !ticket) return FV_E_INVAL;
   std::unique_lock<std::mutex> lk(s->mu);
@@ -566,8 +592,10 @@ int fv_server_get_stats(fv_server* s, fv_server_stats* st, int reset) {
   double busy = s->busy_s;
   if (s->busy_since >= 0) busy += (s->now_us() - s->busy_since) * 1e-6;
   st->busy_s = busy;
+  st->cancelled = s->cancelled;
   if (reset) {
     s->submitted = s->completed = s->failed = s->rejected = s->launches = s->rows_done = 0;
+    s->cancelled = 0;
     s->lat_ms.clear();
     s->peak_admitted = s->admitted;
     s->busy_s = 0;

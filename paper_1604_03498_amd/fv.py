@@ -22,7 +22,7 @@ EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "f
                     "fv_encode_batch", "fv_gmm_set_tuning", "fv_gmm_get_tuning",
                     "fv_kernel_timing", "fv_kernel_timing_read", "fv_server_config_default", "fv_server_create", "fv_server_destroy",
                     "fv_server_submit", "fv_server_submit_device", "fv_server_poll",
-                    "fv_server_next_done",
+                    "fv_server_next_done", "fv_server_cancel",
                     "fv_server_get_stats", "fv_strerror", "fv_last_device_error",
                     "fv_pca_load", "fv_pca_free", "fv_pca_info", "fv_project",
                     "fv_encode_projected", "fv_encode_batch_projected", "fv_em_step",
@@ -58,7 +58,7 @@ class ServerStats(ctypes.Structure):
                 ("queued", ctypes.c_int), ("in_flight", ctypes.c_int),
                 ("admitted_bytes", ctypes.c_size_t), ("peak_admitted_bytes", ctypes.c_size_t),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
-                ("busy_s", ctypes.c_double)]
+                ("busy_s", ctypes.c_double), ("cancelled", ctypes.c_int64)]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfv.so")
@@ -114,9 +114,11 @@ def load():
     lib.fv_server_submit_device.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
     lib.fv_server_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(ReqStats)]
     lib.fv_server_next_done.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
+    lib.fv_server_cancel.argtypes = [vp, ctypes.c_uint64]
     lib.fv_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats), i32]
     for f in (lib.fv_server_create, lib.fv_server_destroy, lib.fv_server_submit,
               lib.fv_server_submit_device, lib.fv_server_poll, lib.fv_server_next_done,
+              lib.fv_server_cancel,
               lib.fv_server_get_stats):
         f.restype = i32
     lib.fv_strerror.argtypes = [i32]
@@ -550,6 +552,15 @@ class Server:
         self._device_inputs.pop(ticket, None)
         stats = {f: getattr(st, f) for f, _ in ReqStats._fields_}
         return rc, (out if rc == OK else None), stats
+
+    def cancel(self, ticket: int) -> int:
+        """fv_server_cancel: OK (withdrawn), PENDING (already in a launch) or E_NOTFOUND."""
+        rc = load().fv_server_cancel(ctypes.c_void_p(self.handle), ctypes.c_uint64(ticket))
+        if rc == OK:
+            self._device_inputs.pop(ticket, None)
+        elif rc not in (PENDING, E_NOTFOUND):
+            _check(rc, "fv_server_cancel")
+        return rc
 
     def next_done(self, timeout_ms: float = -1.0):
         t = ctypes.c_uint64()

@@ -88,6 +88,38 @@ def test_deadline_fails_waiting_requests():
         assert s.stats()["failed"] >= 1
 
 
+def test_cancel_withdraws_queued_and_finished_requests():
+    """fv_server_cancel: a queued request is withdrawn (never launched, never reported); one
+    already in a launch answers PENDING and completes normally; a finished, unpolled one is
+    dropped with its completion notice; unknown or consumed tickets are NOT_FOUND."""
+    def wait_for(pred, timeout=10.0):
+        t0 = time.time()
+        while not pred():
+            assert time.time() - t0 < timeout, "condition never reached"
+            time.sleep(0.002)
+
+    with fake(n_streams=1, max_batch_frames=1, fake_us_per_krow=100000.0) as s:
+        a = s.submit(np.zeros((1000, D), np.float32))            # 100 ms launch
+        wait_for(lambda: s.stats()["in_flight"] == 1)
+        b = s.submit(np.zeros((1000, D), np.float32))
+        c = s.submit(np.zeros((10, D), np.float32))
+        assert s.cancel(b) == fv.OK
+        assert s.cancel(b) == fv.E_NOTFOUND
+        assert s.cancel(a) == fv.PENDING
+        assert s.cancel(987654) == fv.E_NOTFOUND
+        res = drain(s, [a, c])
+        assert res[a][0] == fv.OK and res[c][0] == fv.OK
+        assert s.next_done(50.0) is None                          # b is never reported
+        assert s.poll(b)[0] == fv.E_NOTFOUND
+        e = s.submit(np.zeros((10, D), np.float32))
+        wait_for(lambda: s.stats()["completed"] == 3)
+        assert s.cancel(e) == fv.OK                               # finished, not polled
+        assert s.poll(e)[0] == fv.E_NOTFOUND
+        assert s.next_done(50.0) is None
+        st = s.stats()
+        assert st["cancelled"] == 2 and st["completed"] == 3 and st["queued"] == 0
+
+
 def test_injected_device_error_fails_only_that_batch():
     with fake(n_streams=1, max_batch_frames=1, fake_fail_every=2, fake_us_per_krow=100.0) as s:
         tickets = [s.submit(np.zeros((100, D), np.float32)) for _ in range(6)]
