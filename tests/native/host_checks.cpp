@@ -1,0 +1,145 @@
+// Host-side checks of the C ABI that need no GPU, built with AddressSanitizer and
+// UndefinedBehaviorSanitizer on the host code of every library source: argument validation of
+// the model, encoder, projection and EM entry points, and the serving loop driven by the host
+// executor from several threads (submit, cancel, poll, wait, statistics, destroy with work
+// outstanding).  Exits 0 when every check holds; a sanitizer report aborts the process.
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "fv.h"
+
+static int g_fail = 0;
+#define CHECK(cond)                                                   \
+  do {                                                                \
+    if (!(cond)) {                                                    \
+      std::fprintf(stderr, "FAILED %s:%d: %s\n", __FILE__, __LINE__, #cond); \
+      ++g_fail;                                                       \
+    }                                                                 \
+  } while (0)
+
+static void validation() {
+  const float w[2] = {0.5f, 0.5f}, mu[4] = {0, 0, 1, 1}, var[4] = {1, 1, 1, 1};
+  fv_gmm* g = reinterpret_cast<fv_gmm*>(0x1);
+  CHECK(fv_gmm_load(2, 2, w, mu, var, 0, nullptr) == FV_E_INVAL);
+  CHECK(fv_gmm_load(0, 2, w, mu, var, 0, &g) == FV_E_INVAL && g == nullptr);
+  CHECK(fv_gmm_load(2, 0, w, mu, var, 0, &g) == FV_E_INVAL);
+  CHECK(fv_gmm_load(2, 2, nullptr, mu, var, 0, &g) == FV_E_INVAL);
+  const float wneg[2] = {0.5f, -0.5f}, vzero[4] = {1, 0, 1, 1};
+  const float mnan[4] = {0, NAN, 1, 1};
+  CHECK(fv_gmm_load(2, 2, wneg, mu, var, 0, &g) == FV_E_INVAL);
+  CHECK(fv_gmm_load(2, 2, w, mu, vzero, 0, &g) == FV_E_INVAL);
+  CHECK(fv_gmm_load(2, 2, w, mnan, var, 0, &g) == FV_E_INVAL);
+  int maxK = 0, maxD = 0;
+  fv_limits(&maxK, &maxD);
+  std::vector<float> big((size_t)(maxK + 1) * 2, 1.0f);
+  CHECK(fv_gmm_load(maxK + 1, 2, big.data(), big.data(), big.data(), 0, &g) == FV_E_UNSUPPORTED);
+  CHECK(fv_gmm_free(nullptr) == FV_OK);
+
+  float out[8];
+  const float x[4] = {0, 0, 1, 1};
+  const int64_t off[3] = {0, 1, 2}, bad_off[3] = {0, 2, 1};
+  CHECK(fv_encode(nullptr, x, 2, out, FV_PREC_FP32, 0, nullptr) == FV_E_INVAL);
+  CHECK(fv_encode_batch(nullptr, x, off, 2, out, FV_PREC_FP32, 0, nullptr) == FV_E_INVAL);
+  CHECK(fv_encode_batch(nullptr, x, bad_off, 2, out, FV_PREC_FP32, 0, nullptr) == FV_E_INVAL);
+  float ew[2], em[4], ev[4];
+  double ll = 0;
+  CHECK(fv_em_step(nullptr, x, 2, FV_PREC_FP32, 0.f, 0, nullptr, ew, em, ev, &ll) == FV_E_INVAL);
+  fv_pca* p = nullptr;
+  const float A[4] = {1, 0, 0, 1}, m[2] = {0, 0}, Anan[4] = {1, NAN, 0, 1};
+  CHECK(fv_pca_load(0, 2, A, m, 0, &p) == FV_E_INVAL);
+  CHECK(fv_pca_load(2, 2, Anan, m, 0, &p) == FV_E_INVAL);
+  CHECK(fv_pca_free(nullptr) == FV_OK);
+  CHECK(fv_stream_release(0, nullptr) == FV_OK);  // never used: nothing cached
+  for (int code = -9; code <= 1; ++code) CHECK(fv_strerror(code) != nullptr);
+}
+
+static fv_server* make_fake(int n_streams, double us_per_krow, int fail_every) {
+  fv_server_config c;
+  fv_server_config_default(&c);
+  c.executor = FV_EXEC_FAKE;
+  c.fake_K = 4;
+  c.fake_D = 3;
+  c.fake_us_per_krow = us_per_krow;
+  c.fake_fail_every = fail_every;
+  c.n_streams = n_streams;
+  c.max_queue = 100000;
+  fv_server* s = nullptr;
+  CHECK(fv_server_create(nullptr, &c, &s) == FV_OK && s != nullptr);
+  return s;
+}
+
+static void serving() {
+  const int D = 3, OUT = 2 * 4 * 3;
+  // several submitters, one canceller, one consumer
+  fv_server* s = make_fake(3, 50.0, 7);
+  const int kThreads = 4, kPer = 300;
+  std::vector<std::vector<uint64_t>> mine(kThreads);
+  std::vector<std::thread> th;
+  for (int t = 0; t < kThreads; ++t)
+    th.emplace_back([&, t] {
+      std::vector<float> X((size_t)60 * D, 1.0f + t);
+      for (int i = 0; i < kPer; ++i) {
+        uint64_t tk = 0;
+        const int64_t n = (i * 7 + t) % 60;
+        if (fv_server_submit(s, n ? X.data() : nullptr, n, &tk) == FV_OK) mine[t].push_back(tk);
+      }
+    });
+  for (auto& x : th) x.join();
+  int cancelled = 0;
+  for (int t = 0; t < kThreads; ++t)
+    for (size_t i = 0; i < mine[t].size(); i += 5)
+      if (fv_server_cancel(s, mine[t][i]) == FV_OK) ++cancelled;
+  int64_t total = 0;
+  for (auto& v : mine) total += (int64_t)v.size();
+  std::vector<float> out(OUT);
+  fv_req_stats st;
+  int64_t seen = 0;
+  while (seen + cancelled < total) {
+    uint64_t tk = 0;
+    const int rc = fv_server_next_done(s, 2000.0, &tk);
+    CHECK(rc == FV_OK);
+    if (rc != FV_OK) break;
+    const int pr = fv_server_poll(s, tk, out.data(), &st);
+    CHECK(pr == FV_OK || pr == FV_E_DEVICE);
+    CHECK(st.t_submit_us <= st.t_done_us);
+    ++seen;
+  }
+  fv_server_stats ss;
+  CHECK(fv_server_get_stats(s, &ss, 1) == FV_OK);
+  // a cancelled request may have finished before it was withdrawn (then it is counted as
+  // completed or failed too, but never reported)
+  CHECK(ss.submitted == total && ss.cancelled == cancelled);
+  CHECK(ss.completed + ss.failed >= seen && ss.completed + ss.failed <= seen + cancelled);
+  CHECK(ss.queued == 0 && ss.in_flight == 0);
+  uint64_t tk = 0;
+  std::vector<float> X1(D, 0.f);
+  CHECK(fv_server_submit(s, X1.data(), ((int64_t)1 << 40), &tk) == FV_E_UNSUPPORTED);
+  CHECK(fv_server_poll(s, 123456789, nullptr, nullptr) == FV_E_NOTFOUND);
+  CHECK(fv_server_cancel(s, 123456789) == FV_E_NOTFOUND);
+  CHECK(fv_server_destroy(s) == FV_OK);
+
+  // destroy with queued, running and finished-unpolled work
+  s = make_fake(1, 20000.0, 0);
+  std::vector<float> X(1000 * D, 0.f);
+  for (int i = 0; i < 20; ++i) CHECK(fv_server_submit(s, X.data(), 1000, &tk) == FV_OK);
+  std::this_thread::sleep_for(std::chrono::milliseconds(30));
+  CHECK(fv_server_destroy(s) == FV_OK);
+  CHECK(fv_server_destroy(nullptr) == FV_OK);
+}
+
+int main() {
+  validation();
+  serving();
+  if (g_fail) {
+    std::fprintf(stderr, "%d check(s) failed\n", g_fail);
+    return 1;
+  }
+  std::printf("host checks passed\n");
+  return 0;
+}
