@@ -396,6 +396,10 @@ int fv_server_create(const fv_gmm* gmm, const fv_server_config* cfg, fv_server**
     for (Lane& L : s->lanes) {
       if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
+        for (Lane& M : s->lanes) {  // undo what was created
+          if (M.done) (void)hipEventDestroy(M.done);
+          if (M.stream) (void)hipStreamDestroy(M.stream);
+        }
         (void)hipSetDevice(prev);
         return FV_E_DEVICE;
       }
