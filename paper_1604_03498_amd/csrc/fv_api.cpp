@@ -305,7 +305,7 @@ int normext_groups(const fv::Consts& c) {
 // Rows one second-pass workgroup consumes per round of its waves (32-row tiles).
 int sliced_round(const fv::Consts& c, int prec) {
   switch (prec) {
-    case FV_PREC_FP32: return fv::sliced_rows_per_wave_round();
+    case FV_PREC_FP32: return fv::sliced_rows_per_wave_round(c.DP);
     case FV_PREC_BF16_SPLIT: return fv::kTile * fv::sliced16_waves_bf16s(c.DP);
     case FV_PREC_FP16_SPLIT: return fv::kTile * fv::sliced16_waves_f16s(c.DP);
     default: return fv::kTile * fv::sliced16_waves_bf16(c.DP);
@@ -377,8 +377,8 @@ int xcd_grid(int n) { return (n + 7) / 8 * 8; }
 
 // Chunk length of the second pass for a single frame: about one workgroup per CU over all
 // (chunk, slice) pairs, in whole rounds of the workgroup's 32-row tiles.  Measured on the
-// 8,000-row frame (K = 256, D = 64, FP32): 41 us at one workgroup per CU, 42 us at two, 46 and
-// 51 us at 3/4 and 1/2.
+// 8,000-row frame (K = 256, D = 64, FP32, four-wave workgroups): 41 us at one workgroup per
+// CU, 42 us at two, 46 and 51 us at 3/4 and 1/2.
 int split_single_chunk(int64_t N, int device, int slices, int round) {
   const int64_t target_chunks =
       std::max<int64_t>(1, ((int64_t)device_cu_count(device) + slices - 1) / slices);

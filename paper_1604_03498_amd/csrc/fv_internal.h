@@ -110,8 +110,8 @@ hipError_t launch_normext(const Consts& c, const float* X, bool vec_ok, int64_t 
                           const Item* items, int n_items, int grid, const float2* lse,
                           int64_t lse_stride, float* partials, hipStream_t stream);
 
-// Rows one workgroup of the second pass consumes per round (4 waves x 32-row tiles).
-int sliced_rows_per_wave_round();
+// Rows one FP32 workgroup of the second pass consumes per round (its waves x 32-row tiles).
+int sliced_rows_per_wave_round(int DP);
 
 // Finalize: per frame, the slots of every chunk group are summed in index order in double
 // precision and the group sums are added in order; the totals are turned into u and v,

@@ -7,9 +7,11 @@
 // logits are bit-identical to the first pass), forms the soft assignment directly as
 //     gamma = exp2((logit - M) - log2 Z),   M = max_g m_g,  Z = sum_g s_g 2^(m_g - M),
 // and accumulates the statistics for its slice.  No cross-lane or cross-wave reduction is
-// needed inside the tile loop, so the four waves of a workgroup run independent tiles with
+// needed inside the tile loop, so the waves of a workgroup run independent tiles with
 // wave-private LDS staging and no workgroup barrier until the end of the chunk, where their
-// accumulators are summed (fixed order) and written to the chunk's partial slot.
+// accumulators are summed (fixed order) and written to the chunk's partial slot.  A workgroup
+// has eight waves up to DP = 64 (wave-private tiles of 137 KB of LDS in all; two waves per
+// SIMD, so one wave's loads overlap the other's MFMAs) and four beyond.
 //
 // This path costs one extra E-step (the logits are computed twice) but gives a single frame
 // many more independent workgroups and smaller partial traffic than the fused kernel, and it
@@ -23,10 +25,11 @@ namespace {
 
 using namespace dev;
 
-constexpr int kSliceWaves = 4;
+// Waves per workgroup of the second pass (their LDS tiles must fit together).
+constexpr int slice_waves(int DP) { return DP <= 64 ? 8 : 4; }
 
-template <int DP, bool TH>
-__global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
+template <int DP, int NW, bool TH>
+__global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float2* __restrict__ lse, int G,
     int64_t lse_stride, const float* __restrict__ A32, const float* __restrict__ c32, int Kp,
@@ -35,8 +38,8 @@ __global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
   using IO = TileIO<DP, 64>;
   constexpr int XS = IO::XS;
 
-  __shared__ __attribute__((aligned(16))) float xs[kSliceWaves][kTile * XS];
-  __shared__ __attribute__((aligned(16))) float ls[kSliceWaves][kTile * 2];
+  __shared__ __attribute__((aligned(16))) float xs[NW][kTile * XS];
+  __shared__ __attribute__((aligned(16))) float ls[NW][kTile * 2];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
       for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
     float s0 = 0.f;
 
-    for (int t = w; t < ntiles; t += kSliceWaves) {
+    for (int t = w; t < ntiles; t += NW) {
       const int valid = (nrows - t * kTile) < kTile ? (nrows - t * kTile) : kTile;
       const int64_t trow = row0 + (int64_t)t * kTile;
       f32x4 pre[IO::kPer];
@@ -131,21 +134,21 @@ __global__ __launch_bounds__(64 * kSliceWaves, 2) void sliced_f32_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) red[w * RW + (32 * b + crow(r, h)) * kCompsPerWave + j] = acc[b][r];
     auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(s0), __float_as_uint(s0), false, false);
-    if (h == 0) red[kSliceWaves * RW + w * kCompsPerWave + j] = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    if (h == 0) red[NW * RW + w * kCompsPerWave + j] = __uint_as_float(p[0]) + __uint_as_float(p[1]);
     __syncthreads();
     float* dst = partials + (size_t)it * slot + (size_t)q * kCompsPerWave;
-    for (int e = tid; e < (2 * DP + 1) * kCompsPerWave; e += 64 * kSliceWaves) {
+    for (int e = tid; e < (2 * DP + 1) * kCompsPerWave; e += 64 * NW) {
       const int f = e / kCompsPerWave;
       const int jj = e % kCompsPerWave;
       float v;
       if (f < 2 * DP) {
         v = red[f * kCompsPerWave + jj];
 #pragma unroll
-        for (int ww = 1; ww < kSliceWaves; ++ww) v += red[ww * RW + f * kCompsPerWave + jj];
+        for (int ww = 1; ww < NW; ++ww) v += red[ww * RW + f * kCompsPerWave + jj];
       } else {
-        v = red[kSliceWaves * RW + jj];
+        v = red[NW * RW + jj];
 #pragma unroll
-        for (int ww = 1; ww < kSliceWaves; ++ww) v += red[kSliceWaves * RW + ww * kCompsPerWave + jj];
+        for (int ww = 1; ww < NW; ++ww) v += red[NW * RW + ww * kCompsPerWave + jj];
       }
       dst[(size_t)f * Kp + jj] = v;
     }
@@ -158,12 +161,13 @@ hipError_t launch_sliced_dp(const Consts& c, const float* X, bool vec_ok, int64_
                             const Item* items, int n_items, int grid, const float2* lse,
                             int64_t lse_stride, float* partials, hipStream_t stream) {
   const int slices = c.Kp / kCompsPerWave;
+  constexpr int NW = slice_waves(DP);
   if (c.thresh)
-    hipLaunchKernelGGL((sliced_f32_kernel<DP, true>), dim3(grid, slices), dim3(64 * kSliceWaves),
+    hipLaunchKernelGGL((sliced_f32_kernel<DP, NW, true>), dim3(grid, slices), dim3(64 * NW),
                        0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse,
                        lse_groups(c), lse_stride, c.A32, c.c32, c.Kp, partials);
   else
-    hipLaunchKernelGGL((sliced_f32_kernel<DP, false>), dim3(grid, slices), dim3(64 * kSliceWaves),
+    hipLaunchKernelGGL((sliced_f32_kernel<DP, NW, false>), dim3(grid, slices), dim3(64 * NW),
                        0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse,
                        lse_groups(c), lse_stride, c.A32, c.c32, c.Kp, partials);
   return hipGetLastError();
@@ -171,7 +175,7 @@ hipError_t launch_sliced_dp(const Consts& c, const float* X, bool vec_ok, int64_
 
 }  // namespace
 
-int sliced_rows_per_wave_round() { return kTile * kSliceWaves; }
+int sliced_rows_per_wave_round(int DP) { return kTile * slice_waves(DP); }
 
 hipError_t launch_sliced(const Consts& c, int precision, const float* X, bool vec_ok, int64_t N,
                          int P, const Item* items, int n_items, int grid, const float2* lse,
