@@ -64,6 +64,16 @@ __global__ __launch_bounds__(kRedThreads) void reduce_assemble_kernel(
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
   const int row = wv == 0 ? d : (wv == 1 ? DP + d : 2 * DP);
   const float* base = partials + (size_t)row * Kp + (kok ? k : 0);
+  // the finalize constants of (k, d), loaded up front so that their latency overlaps the sums
+  const int kd = (kok ? k : 0) * D + d;
+  double mu = 0.0, isd = 0.0, ivar = 0.0, cu = 0.0, cv = 0.0;
+  if (wv == 0) {
+    mu = mu64[kd];
+    isd = isd64[kd];
+    ivar = ivar64[kd];
+    cu = cu64[kok ? k : 0];
+    cv = cv64[kok ? k : 0];
+  }
 
   double tot = 0.0;
   for (int g = 0; g < fr.ngroups; g += 2) {
@@ -103,13 +113,11 @@ __global__ __launch_bounds__(kRedThreads) void reduce_assemble_kernel(
     const double S0 = sv[2][lane], S1 = sv[0][lane], S2 = sv[1][lane];
     double u = 0.0, v = 0.0;
     if (fr.nrows > 0) {
-      const int kd = k * D + d;
-      const double m = mu64[kd];
-      const double C1 = S1 - m * S0;                   // sum gamma (x - mu)
-      const double C2 = S2 - m * (2.0 * S1 - m * S0);  // sum gamma (x - mu)^2
+      const double C1 = S1 - mu * S0;                    // sum gamma (x - mu)
+      const double C2 = S2 - mu * (2.0 * S1 - mu * S0);  // sum gamma (x - mu)^2
       const double invN = 1.0 / (double)fr.nrows;
-      u = C1 * isd64[kd] * cu64[k] * invN;
-      v = (C2 * ivar64[kd] - S0) * cv64[k] * invN;
+      u = C1 * isd * cu * invN;
+      v = (C2 * ivar - S0) * cv * invN;
       if (!(flags & kFlagNoPower)) {
         u = (u > 0.0) ? sqrt(u) : ((u < 0.0) ? -sqrt(-u) : 0.0);
         v = (v > 0.0) ? sqrt(v) : ((v < 0.0) ? -sqrt(-v) : 0.0);
@@ -132,6 +140,15 @@ __global__ __launch_bounds__(kThreads) void l2_kernel(float* __restrict__ out,
                                                       int nblk, int len) {
   __shared__ double red[kThreads];
   const int b = blockIdx.y;
+  // this thread's output values are loaded first, so their latency overlaps the norm's sum
+  float* o = out + (size_t)b * len;
+  const int base = blockIdx.x * kThreads * kL2PerThread + threadIdx.x;
+  float v[kL2PerThread];
+#pragma unroll
+  for (int q = 0; q < kL2PerThread; ++q) {
+    const int i = base + q * kThreads;
+    v[q] = i < len ? o[i] : 0.f;
+  }
   // fixed-order sum of the frame's block sums: strided per thread, then a tree
   double ss = 0.0;
   for (int i = threadIdx.x; i < nblk; i += kThreads) ss += normpart[(size_t)b * nblk + i];
@@ -143,12 +160,10 @@ __global__ __launch_bounds__(kThreads) void l2_kernel(float* __restrict__ out,
   }
   const double inv = red[0] > 0.0 ? 1.0 / sqrt(red[0]) : 0.0;
   if (inv == 0.0) return;
-  float* o = out + (size_t)b * len;
-  const int base = blockIdx.x * kThreads * kL2PerThread + threadIdx.x;
 #pragma unroll
   for (int q = 0; q < kL2PerThread; ++q) {
     const int i = base + q * kThreads;
-    if (i < len) o[i] = (float)((double)o[i] * inv);
+    if (i < len) o[i] = (float)((double)v[q] * inv);
   }
 }
 
