@@ -42,7 +42,7 @@ SRC_DIR = os.path.join(HERE, "paper_1604_03498_amd", "csrc")
 TRAFFIC_JSON = os.path.join(HERE, "profiles", "hbm_traffic.json")
 # statistics kernels of each path at D = 64 (as named in rocprofv3 traces)
 STATS_KERNELS = {
-    ("fp32", "split"): ["fused_f32_kernel<64, 8, true, false>", "sliced_f32_kernel<64, false>"],
+    ("fp32", "split"): ["fused_f32_kernel<64, 8, true, false>", "sliced_f32_kernel<64, 8, false>"],
     ("fp32", "fused"): ["fused_f32_kernel<64, 8, false, false>"],
     ("bf16_split", "split"): ["lse16_kernel<64, 8>", "sliced16_kernel<64, false>"],
     ("bf16_split", "fused"): ["fused16t_kernel<64, 8, false>"],
