@@ -261,10 +261,11 @@ hipError_t run_stats(const fv::Consts& c, int prec, const float* X, bool vec_ok,
 }
 
 hipError_t run_lse(const fv::Consts& c, int prec, const float* X, bool vec_ok, int64_t N,
-                   int n_tiles, int grid, float2* lse, int64_t stride, hipStream_t s) {
+                   int n_tiles, int grid, float2* lse, int64_t stride, hipStream_t s,
+                   float* gout = nullptr, int64_t gstride = 0) {
   const fv::Frags16 fr = frags(c, prec);
   switch (prec) {
-    case FV_PREC_FP32: return fv::launch_lse(c, 0, X, vec_ok, N, nullptr, n_tiles, grid, lse, stride, s);
+    case FV_PREC_FP32: return fv::launch_lse(c, 0, X, vec_ok, N, nullptr, n_tiles, grid, lse, stride, s, gout, gstride);
     case FV_PREC_BF16_SPLIT: return fv::launch_lse16_bf16s(c, fr, X, vec_ok, N, nullptr, n_tiles, grid, lse, stride, s);
     case FV_PREC_FP16_SPLIT: return fv::launch_lse16_f16s(c, fr, X, vec_ok, N, nullptr, n_tiles, grid, lse, stride, s);
     default: return fv::launch_lse16_bf16(c, fr, X, vec_ok, N, nullptr, n_tiles, grid, lse, stride, s);
@@ -273,10 +274,11 @@ hipError_t run_lse(const fv::Consts& c, int prec, const float* X, bool vec_ok, i
 
 hipError_t run_sliced(const fv::Consts& c, int prec, const float* X, bool vec_ok, int64_t N, int P,
                       const fv::Item* items, int n_items, int grid, const float2* lse,
-                      int64_t stride, float* partials, hipStream_t s) {
+                      int64_t stride, float* partials, hipStream_t s, const float* gin = nullptr,
+                      int64_t gstride = 0) {
   const fv::Frags16 fr = frags(c, prec);
   switch (prec) {
-    case FV_PREC_FP32: return fv::launch_sliced(c, 0, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
+    case FV_PREC_FP32: return fv::launch_sliced(c, 0, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s, gin, gstride);
     case FV_PREC_BF16_SPLIT: return fv::launch_sliced16_bf16s(c, fr, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
     case FV_PREC_FP16_SPLIT: return fv::launch_sliced16_f16s(c, fr, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
     default: return fv::launch_sliced16_bf16(c, fr, X, vec_ok, N, P, items, n_items, grid, lse, stride, partials, s);
@@ -313,6 +315,15 @@ int sliced_round(const fv::Consts& c, int prec) {
 }
 
 enum class Path { kFused, kSplit };
+
+// The FP32 two-pass path's posterior hand-over (first pass writes e and the row scales, second
+// pass reads them): on unless FV_SPLIT_GAMMA=0 (tests and measurements).  Its buffer,
+// (Kp + Kp / 32) x N floats, is used up to this size; larger frames recompute the E-step.
+constexpr size_t kMaxGammaBytes = (size_t)256 << 20;
+bool split_gamma_enabled() {
+  const char* e = std::getenv("FV_SPLIT_GAMMA");
+  return !(e && e[0] == '0');
+}
 
 // Path override for tests and measurements: FV_PATH=fused|split (default: automatic).
 int path_override() {
@@ -800,13 +811,21 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
   const int G = fv::lse_groups(c);
   const int nblk = fv::finalize_blocks(c);
   const size_t out_len = (size_t)2 * c.K * c.D;
+  // FP32 two-pass with one component group: the first pass also writes the posterior factors
+  // (e and the row scales) and the second pass reads them instead of recomputing the E-step
+  const int64_t gstride = (N + fv::kTile - 1) / fv::kTile * fv::kTile;
+  const size_t gam_bytes = (size_t)(c.Kp + c.Kp / fv::kCompsPerWave) * gstride * 4;
+  const bool gam_path = path == Path::kSplit && !grouped && precision == FV_PREC_FP32 &&
+                        G == 1 && c.DP <= 64 && N > 0 && gam_bytes <= kMaxGammaBytes &&
+                        split_gamma_enabled();
+  const size_t b_gam = gam_path ? align256(gam_bytes) : 0;
   const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
   const size_t b_norm = align256((size_t)nblk * 8);
   const size_t b_lse = (path == Path::kSplit) ? align256((size_t)G * N * 8) : 0;
   const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)N * Din * 4);
   const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256(out_len * 4);
   const size_t b_y = pca ? align256((size_t)N * c.D * 4) : 0;
-  int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_x + b_out + b_y, s);
+  int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_x + b_out + b_y + b_gam, s);
   if (rc) return rc;
   char* base = ws->dev;
   float* partials = reinterpret_cast<float*>(base);
@@ -815,6 +834,8 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
   float* xdev = reinterpret_cast<float*>(base + b_part + b_norm + b_lse);
   float* odev = reinterpret_cast<float*>(base + b_part + b_norm + b_lse + b_x);
   float* ydev = reinterpret_cast<float*>(base + b_part + b_norm + b_lse + b_x + b_out);
+  float* gam = gam_path ? reinterpret_cast<float*>(base + b_part + b_norm + b_lse + b_x + b_out + b_y)
+                        : nullptr;
 
   const float* Xd = X;
   if (!(flags & FV_X_DEVICE) && N > 0) {
@@ -840,13 +861,13 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
       } else {
         const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
         const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
-        FV_HIP(run_lse(c, precision, Fx, vec_ok, N, n_tiles, grid1, lse, N, s));
+        FV_HIP(run_lse(c, precision, Fx, vec_ok, N, n_tiles, grid1, lse, N, s, gam, gstride));
         if (grouped)
           FV_HIP(run_normext(c, precision, Fx, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse,
                              N, partials, s));
         else
           FV_HIP(run_sliced(c, precision, Fx, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
-                            partials, s));
+                            partials, s, gam, gstride));
       }
       timing_end(t0, 0, s);
     }
@@ -863,7 +884,7 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
   key.gmm = gmm->serial;
   key.precision = precision;
   key.flags = flags & kGraphFlags;
-  key.path = (int)path;
+  key.path = (int)path + (gam_path ? 2 : 0);
   key.P = P;
   key.rows = N;
   key.n_items = n_items;

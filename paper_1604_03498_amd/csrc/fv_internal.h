@@ -91,16 +91,22 @@ hipError_t launch_stats(const Consts& c, int precision, const float* X, bool vec
 // First pass of the two-pass path: for every row and component group g, (max_k logit,
 // log2 sum_k 2^(logit - max)) over the group's components, written to lse[g * lse_stride +
 // row].  Items are tiles of 32 rows (`items` device table, or arithmetic over N when null).
+// With gout (FP32, one component group, arithmetic tiles only) the posterior factors are also
+// written for launch_sliced's gin: e component-major [Kp][gstride], then the row scales
+// [Kp / 32][gstride] (gstride >= N, a multiple of 32; (Kp + Kp / 32) * gstride floats).
 hipError_t launch_lse(const Consts& c, int precision, const float* X, bool vec_ok, int64_t N,
                       const Item* items, int n_items, int grid, float2* lse, int64_t lse_stride,
-                      hipStream_t stream);
+                      hipStream_t stream, float* gout = nullptr, int64_t gstride = 0);
 
 // Second pass: statistics per (item, 32-component slice) from the first pass's normalisers,
 // written to the item's partial slot (same layout as launch_stats).  Items hold chunks of P
 // rows (table or arithmetic); grid = (grid, Kp / 32) workgroups.
+// With gin (the first pass's gout, same gstride; P a multiple of 32, arithmetic chunks) gamma
+// = e * f is read instead of recomputed.
 hipError_t launch_sliced(const Consts& c, int precision, const float* X, bool vec_ok, int64_t N,
                          int P, const Item* items, int n_items, int grid, const float2* lse,
-                         int64_t lse_stride, float* partials, hipStream_t stream);
+                         int64_t lse_stride, float* partials, hipStream_t stream,
+                         const float* gin = nullptr, int64_t gstride = 0);
 
 // Second pass over whole component groups: grid = (grid, Kp / (32 * W)) workgroups of W waves
 // (W = Wg, or 4 when Wg = 8 and DP > 64), each owning a chunk of rows (work table or arithmetic,

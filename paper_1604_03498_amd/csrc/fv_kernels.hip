@@ -27,12 +27,18 @@ namespace {
 
 using namespace dev;
 
-template <int DP, int W, bool LSE, bool TH>
+// GOUT (first pass of one component group only): the posterior factors are also written for
+// a second pass that reads them instead of recomputing the E-step: component-major
+// e[k * gstride + row] = 2^((logit - m_w) + lo) (m_w: the row maximum over the wave's 32
+// components) before the workgroup barrier, then the row scales
+// f[(Kp + w) * gstride + row] = 2^(m_w - M) / Z (0 for rows past the frame), so that
+// gamma = e * f, the statistics mode's own product.  gstride is a multiple of 32 rows.
+template <int DP, int W, bool LSE, bool TH, bool GOUT = false>
 __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float* __restrict__ A32,
     const float* __restrict__ c32, int Kp, float* __restrict__ partials,
-    float2* __restrict__ lse, int64_t lse_stride) {
+    float2* __restrict__ lse, int64_t lse_stride, float* __restrict__ gout, int64_t gstride) {
   constexpr int NT = 64 * W;
   constexpr int NB = 2 * DP / 32;  // 32-feature output blocks of the statistics contraction
   // At 8 waves (two per SIMD, 256 registers each) the statistics kernel cannot also hold its
@@ -110,6 +116,15 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
       // published for the cross-wave combine.
       f32x16 e;
       softmax_wave<W>(hi, lo, e, xm, xsum, loc[w], w, j, h);
+      if constexpr (LSE && GOUT) {
+        // rows crow(4g + p, h) = 8g + 4h + p of component `comp`: four 16-byte stores
+        float* ge = gout + (size_t)comp * gstride + row0 + (int64_t)t * kTile + 4 * h;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const f32x4 v = {e[4 * g], e[4 * g + 1], e[4 * g + 2], e[4 * g + 3]};
+          *reinterpret_cast<f32x4*>(ge + 8 * g) = v;
+        }
+      }
       __syncthreads();
       {
         float M, L2Z;
@@ -118,6 +133,10 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
           const int row = crow(j >> 1, h);
           if (w == 0 && !(j & 1) && row < valid)
             lse[(size_t)group * lse_stride + row0 + (int64_t)t * kTile + row] = make_float2(M, L2Z);
+          if constexpr (GOUT) {
+            if (!(j & 1))
+              gout[(size_t)(Kp + w) * gstride + row0 + (int64_t)t * kTile + row] = f;
+          }
         } else {
           if (!(j & 1)) loc[w][crow(j >> 1, h)] = f;
           wave_sync();
@@ -323,29 +342,44 @@ hipError_t normext_dp(const Consts& c, const float* X, bool vec_ok, int64_t N, i
 template <int DP, int W, bool LSE>
 hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
                         const Item* items, int n_items, int grid, int groups, float* partials,
-                        float2* lse, int64_t lse_stride, hipStream_t stream) {
+                        float2* lse, int64_t lse_stride, float* gout, int64_t gstride,
+                        hipStream_t stream) {
   if constexpr (!LSE) {
     if (c.thresh) {
       hipLaunchKernelGGL((fused_f32_kernel<DP, W, false, true>), dim3(grid, groups), dim3(64 * W),
                          0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32,
-                         c.Kp, partials, lse, lse_stride);
+                         c.Kp, partials, lse, lse_stride, nullptr, 0);
       return hipGetLastError();
+    }
+  } else {
+    if (gout != nullptr) {
+      // posterior output up to DP = 64 only (the 8-wave variant would spill above)
+      if constexpr (DP <= 64) {
+        if (groups != 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((fused_f32_kernel<DP, W, true, false, true>), dim3(grid, 1),
+                           dim3(64 * W), 0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items,
+                           c.A32, c.c32, c.Kp, partials, lse, lse_stride, gout, gstride);
+        return hipGetLastError();
+      } else {
+        return hipErrorInvalidValue;
+      }
     }
   }
   hipLaunchKernelGGL((fused_f32_kernel<DP, W, LSE, false>), dim3(grid, groups), dim3(64 * W), 0,
                      stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32, c.Kp,
-                     partials, lse, lse_stride);
+                     partials, lse, lse_stride, nullptr, 0);
   return hipGetLastError();
 }
 
 template <int W, bool LSE>
 hipError_t dispatch_dp(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
                        const Item* items, int n_items, int grid, int groups, float* partials,
-                       float2* lse, int64_t lse_stride, hipStream_t stream) {
+                       float2* lse, int64_t lse_stride, float* gout, int64_t gstride,
+                       hipStream_t stream) {
 #define FV_CASE(DPV)                                                                   \
   case DPV:                                                                            \
     return launch_fused<DPV, W, LSE>(c, X, vec_ok, N, P, items, n_items, grid, groups, \
-                                     partials, lse, lse_stride, stream);
+                                     partials, lse, lse_stride, gout, gstride, stream);
   switch (c.DP) {
     FV_CASE(16)
     FV_CASE(32)
@@ -361,12 +395,13 @@ hipError_t dispatch_dp(const Consts& c, const float* X, bool vec_ok, int64_t N, 
 template <bool LSE>
 hipError_t dispatch_w(int W, const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
                       const Item* items, int n_items, int grid, int groups, float* partials,
-                      float2* lse, int64_t lse_stride, hipStream_t stream) {
+                      float2* lse, int64_t lse_stride, float* gout, int64_t gstride,
+                      hipStream_t stream) {
   switch (W) {
-    case 1: return dispatch_dp<1, LSE>(c, X, vec_ok, N, P, items, n_items, grid, groups, partials, lse, lse_stride, stream);
-    case 2: return dispatch_dp<2, LSE>(c, X, vec_ok, N, P, items, n_items, grid, groups, partials, lse, lse_stride, stream);
-    case 4: return dispatch_dp<4, LSE>(c, X, vec_ok, N, P, items, n_items, grid, groups, partials, lse, lse_stride, stream);
-    case 8: return dispatch_dp<8, LSE>(c, X, vec_ok, N, P, items, n_items, grid, groups, partials, lse, lse_stride, stream);
+    case 1: return dispatch_dp<1, LSE>(c, X, vec_ok, N, P, items, n_items, grid, groups, partials, lse, lse_stride, gout, gstride, stream);
+    case 2: return dispatch_dp<2, LSE>(c, X, vec_ok, N, P, items, n_items, grid, groups, partials, lse, lse_stride, gout, gstride, stream);
+    case 4: return dispatch_dp<4, LSE>(c, X, vec_ok, N, P, items, n_items, grid, groups, partials, lse, lse_stride, gout, gstride, stream);
+    case 8: return dispatch_dp<8, LSE>(c, X, vec_ok, N, P, items, n_items, grid, groups, partials, lse, lse_stride, gout, gstride, stream);
     default: return hipErrorNotSupported;
   }
 }
@@ -379,16 +414,18 @@ hipError_t launch_stats(const Consts& c, int precision, const float* X, bool vec
   if (n_items <= 0) return hipSuccess;
   if (precision != 0 || c.Kp > kMaxWaves * kCompsPerWave) return hipErrorNotSupported;
   return dispatch_w<false>(c.Wg, c, X, vec_ok, N, P, items, n_items, grid, 1, partials, nullptr,
-                           0, stream);
+                           0, nullptr, 0, stream);
 }
 
 hipError_t launch_lse(const Consts& c, int precision, const float* X, bool vec_ok, int64_t N,
                       const Item* items, int n_items, int grid, float2* lse, int64_t lse_stride,
-                      hipStream_t stream) {
+                      hipStream_t stream, float* gout, int64_t gstride) {
   if (n_items <= 0) return hipSuccess;
   if (precision != 0) return hipErrorNotSupported;
+  if (gout != nullptr && (items != nullptr || gstride < N || gstride % kTile != 0))
+    return hipErrorInvalidValue;
   return dispatch_w<true>(c.Wg, c, X, vec_ok, N, kTile, items, n_items, grid, lse_groups(c),
-                          nullptr, lse, lse_stride, stream);
+                          nullptr, lse, lse_stride, gout, gstride, stream);
 }
 
 hipError_t launch_normext(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,

@@ -13,6 +13,10 @@
 // has eight waves up to DP = 64 (wave-private tiles of 137 KB of LDS in all; two waves per
 // SIMD, so one wave's loads overlap the other's MFMAs) and four beyond.
 //
+// GIN: with one component group the first pass can also write the posterior factors (e,
+// component-major [Kp][gstride], and the row scales f, [Kp / 32][gstride]); the workgroup then
+// forms gamma = e * f for its slice instead of recomputing the E-step.
+//
 // This path costs one extra E-step (the logits are computed twice) but gives a single frame
 // many more independent workgroups and smaller partial traffic than the fused kernel, and it
 // is the only path for more than 256 components.
@@ -28,12 +32,12 @@ using namespace dev;
 // Waves per workgroup of the second pass (their LDS tiles must fit together).
 constexpr int slice_waves(int DP) { return DP <= 64 ? 8 : 4; }
 
-template <int DP, int NW, bool TH>
+template <int DP, int NW, bool TH, bool GIN>
 __global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float2* __restrict__ lse, int G,
     int64_t lse_stride, const float* __restrict__ A32, const float* __restrict__ c32, int Kp,
-    float* __restrict__ partials) {
+    const float* __restrict__ gin, int64_t gstride, float* __restrict__ partials) {
   constexpr int NB = 2 * DP / 32;
   using IO = TileIO<DP, 64>;
   constexpr int XS = IO::XS;
@@ -49,9 +53,12 @@ __global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
   const int q = blockIdx.y;  // component slice
   const int comp = q * kCompsPerWave + j;
 
-  float areg[DP];
-  load_areg<DP>(areg, A32, q, lane);
-  const float cval = c32[comp];
+  float areg[GIN ? 1 : DP];
+  float cval = 0.f;
+  if constexpr (!GIN) {
+    load_areg<DP>(areg, A32, q, lane);
+    cval = c32[comp];
+  }
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
   float* xw = xs[w];
   float* lw = ls[w];
@@ -81,9 +88,24 @@ __global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
       const int64_t trow = row0 + (int64_t)t * kTile;
       f32x4 pre[IO::kPer];
       IO::fetch(pre, X, D, vec_ok != 0, trow, valid, lane);
+      f32x16 gam;
+      if constexpr (GIN) {
+        // register 4g + p holds row crow(4g + p, h) = 8g + 4h + p: four 16-byte loads each of
+        // e (this lane's component) and of the row scales (this slice); rows past the frame
+        // have scale 0
+        const float* ge = gin + (size_t)comp * gstride + trow + 4 * h;
+        const float* gf = gin + (size_t)(Kp + q) * gstride + trow + 4 * h;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const f32x4 ev = *reinterpret_cast<const f32x4*>(ge + 8 * g);
+          const f32x4 fv = *reinterpret_cast<const f32x4*>(gf + 8 * g);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) gam[4 * g + p] = ev[p] * fv[p];
+        }
+      }
       // per-row normaliser from the first pass, merged over component groups (the same
       // arithmetic as merge_lse, one group at a time to save registers)
-      if (lane < kTile) {
+      if (!GIN && lane < kTile) {
         float M = 0.f, L2Z = INFINITY;  // rows past the tile end get gamma = 0
         if (lane < valid) {
           float2 v = lse[trow + lane];
@@ -103,19 +125,20 @@ __global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
       IO::store(xw, pre, lane);
       wave_sync();
 
-      f32x16 hi, lo;
-      estep_f32<DP>(xw + j * XS + DP * h, areg, cval, hi, lo);
-      f32x16 gam;
+      if constexpr (!GIN) {
+        f32x16 hi, lo;
+        estep_f32<DP>(xw + j * XS + DP * h, areg, cval, hi, lo);
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        const f32x4 a = *reinterpret_cast<const f32x4*>(lw + 2 * (8 * qq + 4 * h));
-        const f32x4 b = *reinterpret_cast<const f32x4*>(lw + 2 * (8 * qq + 4 * h) + 4);
-        const float Ms[4] = {a[0], a[2], b[0], b[2]};
-        const float Ls[4] = {a[1], a[3], b[1], b[3]};
+        for (int qq = 0; qq < 4; ++qq) {
+          const f32x4 a = *reinterpret_cast<const f32x4*>(lw + 2 * (8 * qq + 4 * h));
+          const f32x4 b = *reinterpret_cast<const f32x4*>(lw + 2 * (8 * qq + 4 * h) + 4);
+          const float Ms[4] = {a[0], a[2], b[0], b[2]};
+          const float Ls[4] = {a[1], a[3], b[1], b[3]};
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const int r = 4 * qq + p;
-          gam[r] = fast_exp2(((hi[r] - Ms[p]) + lo[r]) - Ls[p]);
+          for (int p = 0; p < 4; ++p) {
+            const int r = 4 * qq + p;
+            gam[r] = fast_exp2(((hi[r] - Ms[p]) + lo[r]) - Ls[p]);
+          }
         }
       }
       if (TH) apply_threshold(gam, kTau);
@@ -156,20 +179,40 @@ __global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
   }
 }
 
+template <int DP, bool TH, bool GIN>
+void launch_sliced_k(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
+                     const Item* items, int n_items, int grid, const float2* lse,
+                     int64_t lse_stride, const float* gin, int64_t gstride, float* partials,
+                     hipStream_t stream) {
+  constexpr int NW = slice_waves(DP);
+  hipLaunchKernelGGL((sliced_f32_kernel<DP, NW, TH, GIN>), dim3(grid, c.Kp / kCompsPerWave),
+                     dim3(64 * NW), 0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse,
+                     lse_groups(c), lse_stride, c.A32, c.c32, c.Kp, gin, gstride, partials);
+}
+
 template <int DP>
 hipError_t launch_sliced_dp(const Consts& c, const float* X, bool vec_ok, int64_t N, int P,
                             const Item* items, int n_items, int grid, const float2* lse,
-                            int64_t lse_stride, float* partials, hipStream_t stream) {
-  const int slices = c.Kp / kCompsPerWave;
-  constexpr int NW = slice_waves(DP);
-  if (c.thresh)
-    hipLaunchKernelGGL((sliced_f32_kernel<DP, NW, true>), dim3(grid, slices), dim3(64 * NW),
-                       0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse,
-                       lse_groups(c), lse_stride, c.A32, c.c32, c.Kp, partials);
-  else
-    hipLaunchKernelGGL((sliced_f32_kernel<DP, NW, false>), dim3(grid, slices), dim3(64 * NW),
-                       0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse,
-                       lse_groups(c), lse_stride, c.A32, c.c32, c.Kp, partials);
+                            int64_t lse_stride, const float* gin, int64_t gstride,
+                            float* partials, hipStream_t stream) {
+  if (gin != nullptr && (lse_groups(c) != 1 || items != nullptr || P % kTile != 0 ||
+                         gstride < N || gstride % kTile != 0))
+    return hipErrorInvalidValue;
+  if (gin != nullptr) {
+    if constexpr (DP <= 64) {  // the first pass writes posterior factors up to DP = 64
+      if (c.thresh)
+        launch_sliced_k<DP, true, true>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, gin, gstride, partials, stream);
+      else
+        launch_sliced_k<DP, false, true>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, gin, gstride, partials, stream);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else {
+    if (c.thresh)
+      launch_sliced_k<DP, true, false>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, nullptr, 0, partials, stream);
+    else
+      launch_sliced_k<DP, false, false>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, nullptr, 0, partials, stream);
+  }
   return hipGetLastError();
 }
 
@@ -179,16 +222,17 @@ int sliced_rows_per_wave_round(int DP) { return kTile * slice_waves(DP); }
 
 hipError_t launch_sliced(const Consts& c, int precision, const float* X, bool vec_ok, int64_t N,
                          int P, const Item* items, int n_items, int grid, const float2* lse,
-                         int64_t lse_stride, float* partials, hipStream_t stream) {
+                         int64_t lse_stride, float* partials, hipStream_t stream,
+                         const float* gin, int64_t gstride) {
   if (n_items <= 0) return hipSuccess;
   if (precision != 0) return hipErrorNotSupported;
   switch (c.DP) {
-    case 16: return launch_sliced_dp<16>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
-    case 32: return launch_sliced_dp<32>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
-    case 48: return launch_sliced_dp<48>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
-    case 64: return launch_sliced_dp<64>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
-    case 80: return launch_sliced_dp<80>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
-    case 96: return launch_sliced_dp<96>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, partials, stream);
+    case 16: return launch_sliced_dp<16>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, gin, gstride, partials, stream);
+    case 32: return launch_sliced_dp<32>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, gin, gstride, partials, stream);
+    case 48: return launch_sliced_dp<48>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, gin, gstride, partials, stream);
+    case 64: return launch_sliced_dp<64>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, gin, gstride, partials, stream);
+    case 80: return launch_sliced_dp<80>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, gin, gstride, partials, stream);
+    case 96: return launch_sliced_dp<96>(c, X, vec_ok, N, P, items, n_items, grid, lse, lse_stride, gin, gstride, partials, stream);
     default: return hipErrorInvalidValue;
   }
 }

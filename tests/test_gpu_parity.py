@@ -136,6 +136,35 @@ def test_paths_agree(fv, monkeypatch):
     assert e["e_inf"] <= 5e-6 and e["e_2"] <= 5e-6
 
 
+@pytest.mark.parametrize("K,D,N,flags", [(256, 64, 8000, 0), (64, 64, 2000, 0), (256, 48, 1001, 0),
+                                         (33, 17, 77, 0), (256, 64, 8000, 32)])
+def test_split_posterior_handover(fv, K, D, N, flags, monkeypatch):
+    """FP32 two-pass frames with one component group hand the posterior factors (e and the row
+    scales) from the first pass to the second instead of recomputing the E-step there
+    (FV_SPLIT_GAMMA=0 forces the recompute).  Both meet the FP32 gate against the oracle (the
+    threshold form against the oracle's tau mode), and agree with each other to the same
+    order; ragged tails and a few-row frame included."""
+    import torch
+    say(f"[gpu] split posterior hand-over K={K} D={D} N={N} flags={flags}")
+    g = fvsynth.gmm(K, D, 1)
+    Xn = fvsynth.frame(g, N, 9, 0.05)
+    X = torch.from_numpy(Xn).cuda()
+    h = _gmm(fv, g)
+    monkeypatch.setenv("FV_PATH", "split")
+    monkeypatch.setenv("FV_SPLIT_GAMMA", "1")
+    a = fv.encode(h, X, flags=flags).cpu().numpy()
+    monkeypatch.setenv("FV_SPLIT_GAMMA", "0")
+    b = fv.encode(h, X, flags=flags).cpu().numpy()
+    ref = oracle.encode_gmm(Xn, g, tau=fv.THRESHOLD_TAU if flags else None)
+    ea, eb, eab = errors(a, ref), errors(b, ref), errors(a, b)
+    say(f"  hand-over {ea['e_inf']:.2e}/{ea['e_2']:.2e}, recompute {eb['e_inf']:.2e}/{eb['e_2']:.2e}, "
+        f"between {eab['e_inf']:.2e}")
+    assert np.all(np.isfinite(a))
+    for e in (ea, eb):
+        assert e["e_inf"] <= 1e-5 and e["e_2"] <= 1e-5, e
+    assert eab["e_inf"] <= 5e-6 and eab["e_2"] <= 5e-6
+
+
 def test_batch_matches_oracle_and_is_frame_relative(fv, path):
     import torch
     say(f"[gpu] batch path={path}")
