@@ -149,6 +149,16 @@ int fv_gmm_set_tuning(fv_gmm* gmm, const fv_tuning* tuning); /* NULL restores th
 int fv_gmm_get_tuning(const fv_gmm* gmm, fv_tuning* tuning);
 
 /*
+ * Environment switches read at each call (for tests and measurements; results stay within the
+ * gates either way):
+ *   FV_PATH=fused|split   force the single-pass or two-pass path where both exist
+ *   FV_BATCH_CHUNK=n      rows per frame-relative chunk of fv_encode_batch (multiple of 128)
+ *   FV_GRAPH=0            never capture or replay graphs
+ *   FV_SPLIT_GAMMA=0      FP32 two-pass frames recompute the E-step in the second pass instead
+ *                         of reading the posterior factors the first pass wrote
+ */
+
+/*
  * Kernel timing (instrumentation for benchmarks and profilers).  fv_kernel_timing(1) resets
  * the counters and starts bracketing every launch of libfv's kernels with HIP events on the
  * stream the kernel is launched on; fv_kernel_timing(0) stops.  fv_kernel_timing_read waits
