@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           const f32x4 v = {e[4 * g], e[4 * g + 1], e[4 * g + 2], e[4 * g + 3]};
-          *reinterpret_cast<f32x4*>(ge + 8 * g) = v;
+          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ge + 8 * g));
         }
       }
       __syncthreads();
