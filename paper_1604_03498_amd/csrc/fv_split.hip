@@ -173,7 +173,7 @@ __global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
 #pragma unroll
         for (int ww = 1; ww < NW; ++ww) v += red[NW * RW + ww * kCompsPerWave + jj];
       }
-      dst[(size_t)f * Kp + jj] = v;
+      __builtin_nontemporal_store(v, &dst[(size_t)f * Kp + jj]);  // read by another kernel
     }
     __syncthreads();
   }
