@@ -17,9 +17,9 @@
 // component-major [Kp][gstride], and the row scales f, [Kp / 32][gstride]); the workgroup then
 // forms gamma = e * f for its slice instead of recomputing the E-step.
 //
-// This path costs one extra E-step (the logits are computed twice) but gives a single frame
-// many more independent workgroups and smaller partial traffic than the fused kernel, and it
-// is the only path for more than 256 components.
+// Without GIN this path costs one extra E-step (the logits are computed twice); either way it
+// gives a single frame many more independent workgroups and smaller partial traffic than the
+// fused kernel, and it is the only path for more than 256 components.
 #include <math.h>
 
 #include "fv_device.h"
