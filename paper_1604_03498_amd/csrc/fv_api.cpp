@@ -100,8 +100,10 @@ struct GraphKey {
   const void* dev = nullptr;
   const void* pinned = nullptr;
   uint64_t pca = 0;  // 0: no projection
+  int cap = 0;       // FV_MAX_GRID in force at capture (0: none)
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && gmm == o.gmm && precision == o.precision && flags == o.flags &&
+           cap == o.cap &&
            path == o.path && P == o.P && rows == o.rows && B == o.B && n_items == o.n_items &&
            n_groups == o.n_groups && X == o.X && out == o.out && dev == o.dev &&
            pinned == o.pinned && pca == o.pca;
@@ -323,6 +325,16 @@ constexpr size_t kMaxGammaBytes = (size_t)256 << 20;
 bool split_gamma_enabled() {
   const char* e = std::getenv("FV_SPLIT_GAMMA");
   return !(e && e[0] == '0');
+}
+
+// Persistent-grid cap for tests and measurements: FV_MAX_GRID=n limits the first grid
+// dimension of every statistics launch to n workgroups, so each workgroup loops over several
+// work items (the kernels are grid-stride over their items; results do not depend on it).
+int grid_cap(int g) {
+  const char* e = std::getenv("FV_MAX_GRID");
+  if (!e) return g;
+  const int x = std::atoi(e);
+  return x >= 1 ? std::min(g, x) : g;
 }
 
 // Path override for tests and measurements: FV_PATH=fused|split (default: automatic).
@@ -628,10 +640,23 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
   std::vector<uint16_t> abh(nfrag, 0), abl(nfrag, 0), ahh(nfrag, 0), ahl(nfrag, 0);
   bool f16_fits = true;
   std::vector<double> mu64(KD), isd64(KD), ivar64(KD), cu64(K), cv64(K);
+  // model centre m0 = sum_k w_k mu_k / sum_k w_k, rounded to float: the kernels encode x - m0
+  // against the means mu - m0 (exact in double), which leaves the Fisher vector unchanged and
+  // keeps x, x^2, the operand entries and the raw moments small for data far from the origin
+  std::vector<float> cen((size_t)DP, 0.f);
+  {
+    double wsum = 0.0;
+    for (int k = 0; k < K; ++k) wsum += (double)priors[k];
+    for (int d = 0; d < D; ++d) {
+      double a = 0.0;
+      for (int k = 0; k < K; ++k) a += (double)priors[k] * (double)means[(size_t)k * D + d];
+      cen[d] = (float)(a / wsum);
+    }
+  }
   for (int k = 0; k < K; ++k) {
     double logdet = 0.0, quad = 0.0;
     for (int d = 0; d < D; ++d) {
-      const double m = means[(size_t)k * D + d];
+      const double m = (double)means[(size_t)k * D + d] - (double)cen[d];
       const double v = variances[(size_t)k * D + d];
       const double iv = 1.0 / v;
       A[(size_t)d * Kp + k] = (float)(m * iv * LOG2E);
@@ -681,7 +706,7 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
     off = align256(off + bytes);
     return o;
   };
-  const size_t oA = take(nA * 4), oc = take((size_t)Kp * 4);
+  const size_t oA = take(nA * 4), oc = take((size_t)Kp * 4), oCen = take((size_t)DP * 4);
   const size_t oBH = take(nfrag * 2), oBL = take(nfrag * 2), oHH = take(nfrag * 2), oHL = take(nfrag * 2);
   const size_t oMu = take(KD * 8), oIsd = take(KD * 8), oIvar = take(KD * 8);
   const size_t oCu = take((size_t)K * 8), oCv = take((size_t)K * 8);
@@ -696,6 +721,7 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
   std::vector<char> host(total, 0);
   std::memcpy(host.data() + oA, Af.data(), nA * 4);
   std::memcpy(host.data() + oc, cc.data(), (size_t)Kp * 4);
+  std::memcpy(host.data() + oCen, cen.data(), (size_t)DP * 4);
   std::memcpy(host.data() + oBH, abh.data(), nfrag * 2);
   std::memcpy(host.data() + oBL, abl.data(), nfrag * 2);
   std::memcpy(host.data() + oHH, ahh.data(), nfrag * 2);
@@ -712,6 +738,7 @@ int fv_gmm_load(int K, int D, const float* priors, const float* means, const flo
   }
   c.A32 = reinterpret_cast<const float*>(blk + oA);
   c.c32 = reinterpret_cast<const float*>(blk + oc);
+  c.cen = reinterpret_cast<const float*>(blk + oCen);
   c.Abf_hi = reinterpret_cast<const uint16_t*>(blk + oBH);
   c.Abf_lo = reinterpret_cast<const uint16_t*>(blk + oBL);
   c.Ah_hi = reinterpret_cast<const uint16_t*>(blk + oHH);
@@ -779,55 +806,103 @@ int fv_gmm_info(const fv_gmm* gmm, int* K, int* D, int* device) {
   return FV_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The single-frame launch plan: path, chunk length and the scratch each buffer takes.
+struct SinglePlan {
+  Path path = Path::kSplit;
+  bool grouped = false, gam_path = false;
+  int P = fv::kTile, n_items = 0, n_groups = 0, G = 1, nblk = 0;
+  int64_t gstride = 0;
+  size_t b_gam = 0, b_part = 0, b_norm = 0, b_lse = 0;
+  size_t scratch() const { return b_part + b_norm + b_lse + b_gam; }
+};
+
+SinglePlan plan_single(const fv_gmm* gmm, const fv::Consts& c, int64_t N, int precision,
+                       Path path, bool allow_gam) {
+  SinglePlan p;
+  p.path = path;
+  const int slices = c.Kp / fv::kCompsPerWave;
+  // the two-pass path's second pass: component-sliced workgroups up to 256 components (more
+  // parallelism for one frame), whole component groups beyond
+  p.grouped = c.Kp > fv::kFusedMaxK;
+  if (N > 0)
+    p.P = (path == Path::kFused) ? fused_single_chunk(N, gmm->device, c.Wg)
+          : p.grouped            ? normext_single_chunk(N, gmm->device, normext_groups(c))
+                                 : split_single_chunk(N, gmm->device, slices, sliced_round(c, precision));
+  p.n_items = N > 0 ? (int)((N + p.P - 1) / p.P) : 0;
+  p.n_groups = (p.n_items + fv::kGroupItems - 1) / fv::kGroupItems;
+  p.G = fv::lse_groups(c);
+  p.nblk = fv::finalize_blocks(c);
+  // FP32 two-pass with one component group: the first pass also writes the posterior factors
+  // (e and the row scales) and the second pass reads them instead of recomputing the E-step
+  p.gstride = (N + fv::kTile - 1) / fv::kTile * fv::kTile;
+  const size_t gam_bytes = (size_t)(c.Kp + c.Kp / fv::kCompsPerWave) * p.gstride * 4;
+  p.gam_path = allow_gam && path == Path::kSplit && !p.grouped && precision == FV_PREC_FP32 &&
+               p.G == 1 && c.DP <= 64 && N > 0 && gam_bytes <= kMaxGammaBytes &&
+               split_gamma_enabled();
+  p.b_gam = p.gam_path ? align256(gam_bytes) : 0;
+  p.b_part = align256((size_t)p.n_items * fv::slot_floats(c) * 4);
+  p.b_norm = align256((size_t)p.nblk * 8);
+  p.b_lse = (path == Path::kSplit) ? align256((size_t)p.G * N * 8) : 0;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
 // fv_encode, with the projection prologue when pca is non-null (X then has pca->Din columns).
+// With ext non-null (the allocation-free entry point) every intermediate lives in the ext_cap
+// bytes at ext: X and out must be in device memory, nothing is allocated, no graph is captured
+// and no timing event is recorded; the plan falls back to the two-pass path and then to the
+// E-step recompute when the preferred one does not fit, and a frame that fits neither is
+// refused with FV_E_UNSUPPORTED.
 static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int64_t N,
-                       float* out, int precision, unsigned flags, void* hip_stream) {
+                       float* out, int precision, unsigned flags, void* hip_stream,
+                       char* ext = nullptr, size_t ext_cap = 0) {
   if (!gmm || !out || N < 0 || (N > 0 && !X)) return FV_E_INVAL;
   if (const int fs = fv_form_status(gmm, precision)) return fs;
   if (flags & ~kAllFlags) return FV_E_INVAL;
   if (pca && (pca->D != gmm->D || pca->device != gmm->device)) return FV_E_INVAL;
+  if (ext && (pca || !(flags & FV_X_DEVICE) || !(flags & FV_OUT_DEVICE))) return FV_E_INVAL;
   const fv::Consts c = call_consts(gmm, flags);
   const int Din = pca ? pca->Din : c.D;
   if (N > ((int64_t)1 << 40) / std::max(Din, c.D)) return FV_E_UNSUPPORTED;
   DeviceGuard g(gmm->device);
   if (g.status() != hipSuccess) return hip_fail(g.status());
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  Workspace* ws = workspace_for(gmm->device, s);
-  if (!ws) return FV_E_NOMEM;
-  std::lock_guard<std::mutex> lk(ws->mu);
+  Workspace* ws = nullptr;
+  std::unique_lock<std::mutex> lk;
+  if (!ext) {
+    ws = workspace_for(gmm->device, s);
+    if (!ws) return FV_E_NOMEM;
+    lk = std::unique_lock<std::mutex>(ws->mu);
+  }
 
-  const Path path = choose_single(gmm, N, precision);
-  const int slices = c.Kp / fv::kCompsPerWave;
-  int P = fv::kTile;
-  // the two-pass path's second pass: component-sliced workgroups up to 256 components (more
-  // parallelism for one frame), whole component groups beyond
-  const bool grouped = c.Kp > fv::kFusedMaxK;
-  if (N > 0)
-    P = (path == Path::kFused) ? fused_single_chunk(N, gmm->device, c.Wg)
-        : grouped              ? normext_single_chunk(N, gmm->device, normext_groups(c))
-                               : split_single_chunk(N, gmm->device, slices, sliced_round(c, precision));
-  const int n_items = N > 0 ? (int)((N + P - 1) / P) : 0;
-  const int n_groups = (n_items + fv::kGroupItems - 1) / fv::kGroupItems;
-  const int G = fv::lse_groups(c);
-  const int nblk = fv::finalize_blocks(c);
+  SinglePlan pl = plan_single(gmm, c, N, precision, choose_single(gmm, N, precision), true);
+  if (ext && pl.scratch() > ext_cap && pl.path == Path::kFused)
+    pl = plan_single(gmm, c, N, precision, Path::kSplit, true);
+  if (ext && pl.scratch() > ext_cap && pl.gam_path)
+    pl = plan_single(gmm, c, N, precision, pl.path, false);
+  if (ext && pl.scratch() > ext_cap) return FV_E_UNSUPPORTED;
+  const Path path = pl.path;
+  const bool grouped = pl.grouped, gam_path = pl.gam_path;
+  const int P = pl.P, n_items = pl.n_items, n_groups = pl.n_groups;
+  const int64_t gstride = pl.gstride;
   const size_t out_len = (size_t)2 * c.K * c.D;
-  // FP32 two-pass with one component group: the first pass also writes the posterior factors
-  // (e and the row scales) and the second pass reads them instead of recomputing the E-step
-  const int64_t gstride = (N + fv::kTile - 1) / fv::kTile * fv::kTile;
-  const size_t gam_bytes = (size_t)(c.Kp + c.Kp / fv::kCompsPerWave) * gstride * 4;
-  const bool gam_path = path == Path::kSplit && !grouped && precision == FV_PREC_FP32 &&
-                        G == 1 && c.DP <= 64 && N > 0 && gam_bytes <= kMaxGammaBytes &&
-                        split_gamma_enabled();
-  const size_t b_gam = gam_path ? align256(gam_bytes) : 0;
-  const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
-  const size_t b_norm = align256((size_t)nblk * 8);
-  const size_t b_lse = (path == Path::kSplit) ? align256((size_t)G * N * 8) : 0;
+  const size_t b_gam = pl.b_gam, b_part = pl.b_part, b_norm = pl.b_norm, b_lse = pl.b_lse;
   const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)N * Din * 4);
   const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256(out_len * 4);
   const size_t b_y = pca ? align256((size_t)N * c.D * 4) : 0;
-  int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_x + b_out + b_y + b_gam, s);
-  if (rc) return rc;
-  char* base = ws->dev;
+  int rc = FV_OK;
+  if (!ext) {
+    rc = ensure_dev(ws, b_part + b_norm + b_lse + b_x + b_out + b_y + b_gam, s);
+    if (rc) return rc;
+  }
+  char* base = ext ? ext : ws->dev;
   float* partials = reinterpret_cast<float*>(base);
   double* normpart = reinterpret_cast<double*>(base + b_part);
   float2* lse = reinterpret_cast<float2*>(base + b_part + b_norm);
@@ -850,33 +925,40 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
 
   auto enqueue = [&]() -> int {
     if (pca && N > 0) {
-      hipEvent_t tp = timing_begin(s);
+      hipEvent_t tp = ext ? nullptr : timing_begin(s);
       FV_HIP(fv::launch_project(pca->p, Xd, N, ydev, project_grid(gmm->device, N), s));
       timing_end(tp, 2, s);
     }
     if (n_items > 0) {
-      hipEvent_t t0 = timing_begin(s);
+      hipEvent_t t0 = ext ? nullptr : timing_begin(s);
       if (path == Path::kFused) {
-        FV_HIP(run_stats(c, precision, Fx, vec_ok, N, P, nullptr, n_items, n_items, partials, s));
+        FV_HIP(run_stats(c, precision, Fx, vec_ok, N, P, nullptr, n_items, grid_cap(n_items), partials, s));
       } else {
         const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
-        const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
+        const int grid1 = grid_cap(std::min(n_tiles, resident_fused(gmm->device, c.Wg)));
         FV_HIP(run_lse(c, precision, Fx, vec_ok, N, n_tiles, grid1, lse, N, s, gam, gstride));
+        const int grid2 = grid_cap(xcd_grid(n_items));
         if (grouped)
-          FV_HIP(run_normext(c, precision, Fx, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse,
-                             N, partials, s));
+          FV_HIP(run_normext(c, precision, Fx, vec_ok, N, P, nullptr, n_items, grid2, lse, N,
+                             partials, s));
         else
-          FV_HIP(run_sliced(c, precision, Fx, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
+          FV_HIP(run_sliced(c, precision, Fx, vec_ok, N, P, nullptr, n_items, grid2, lse, N,
                             partials, s, gam, gstride));
       }
       timing_end(t0, 0, s);
     }
     fv::Frame single{N, 0, n_items, 0, n_groups};
-    hipEvent_t t1 = timing_begin(s);
+    hipEvent_t t1 = ext ? nullptr : timing_begin(s);
     FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, nullptr, flags, Od, normpart, s));
     timing_end(t1, 1, s);
     return FV_OK;
   };
+  if (ext) {
+    rc = enqueue();
+    if (rc) return rc;
+    if (!(flags & FV_ASYNC)) FV_HIP(hipStreamSynchronize(s));
+    return FV_OK;
+  }
   const bool use_graph = graphs_enabled() && s != nullptr && (flags & FV_X_DEVICE) &&
                          (flags & FV_OUT_DEVICE) && !timing_enabled();
   GraphKey key;
@@ -893,6 +975,7 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
   key.out = Od;
   key.dev = ws->dev;
   key.pca = pca ? pca->serial : 0;
+  key.cap = grid_cap(1 << 30) == (1 << 30) ? 0 : grid_cap(1 << 30);
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   if (!(flags & FV_OUT_DEVICE))
@@ -1013,14 +1096,14 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
     if (n_items > 0) {
       hipEvent_t t0 = timing_begin(s);
       if (path == Path::kFused) {
-        const int grid = std::max(1, std::min(n_items, resident_fused(gmm->device, c.Wg)));
+        const int grid = grid_cap(std::max(1, std::min(n_items, resident_fused(gmm->device, c.Wg))));
         FV_HIP(run_stats(c, precision, Fx, vec_ok, rows, P, ditems, n_items, grid, partials, s));
       } else {
         const int n_tiles = (int)((rows + fv::kTile - 1) / fv::kTile);
-        const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
+        const int grid1 = grid_cap(std::min(n_tiles, resident_fused(gmm->device, c.Wg)));
         FV_HIP(run_lse(c, precision, Fx, vec_ok, rows, n_tiles, grid1, lse, rows, s));
         const int groups = normext_groups(c);
-        const int grid2 = xcd_grid(std::max(1, std::min(n_items, (device_cu_count(gmm->device) + groups - 1) / groups)));
+        const int grid2 = grid_cap(xcd_grid(std::max(1, std::min(n_items, (device_cu_count(gmm->device) + groups - 1) / groups))));
         FV_HIP(run_normext(c, precision, Fx, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
       }
       timing_end(t0, 0, s);
@@ -1049,6 +1132,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   key.dev = ws->dev;
   key.pinned = ws->pinned;
   key.pca = pca ? pca->serial : 0;
+  key.cap = grid_cap(1 << 30) == (1 << 30) ? 0 : grid_cap(1 << 30);
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   FV_HIP(hipEventRecord(ws->pin_done, s));
@@ -1063,6 +1147,27 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
               unsigned flags, void* hip_stream) {
   return encode_impl(gmm, nullptr, X, N, out, precision, flags, hip_stream);
 }
+
+}  // extern "C"
+
+namespace fv {
+int encode_with_scratch(const fv_gmm* gmm, const float* X, int64_t N, float* out, int precision,
+                        unsigned flags, void* hip_stream, char* scratch, size_t scratch_bytes) {
+  if (!gmm || !scratch) return FV_E_INVAL;
+  if ((flags & (FV_X_DEVICE | FV_OUT_DEVICE)) != (FV_X_DEVICE | FV_OUT_DEVICE)) return FV_E_INVAL;
+  return encode_impl(gmm, nullptr, X, N, out, precision, flags, hip_stream, scratch,
+                     scratch_bytes);
+}
+
+int set_device(int device) {
+  const hipError_t e = hipSetDevice(device);
+  return e == hipSuccess ? FV_OK : hip_fail(e);
+}
+
+int device_error(hipError_t e) { return hip_fail(e); }
+}  // namespace fv
+
+extern "C" {
 
 int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, int B, float* out,
                     int precision, unsigned flags, void* hip_stream) {
@@ -1240,13 +1345,14 @@ int fv_em_step(const fv_gmm* gmm, const float* X, int64_t N, int precision, floa
   if ((reinterpret_cast<uintptr_t>(Xd) & 3) != 0) return FV_E_INVAL;
   const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xd) & 15) == 0);
   const int n_tiles = (int)((N + fv::kTile - 1) / fv::kTile);
-  const int grid1 = std::min(n_tiles, resident_fused(gmm->device, c.Wg));
+  const int grid1 = grid_cap(std::min(n_tiles, resident_fused(gmm->device, c.Wg)));
   FV_HIP(run_lse(c, precision, Xd, vec_ok, N, n_tiles, grid1, lse, N, s));
+  const int grid2 = grid_cap(xcd_grid(n_items));
   if (grouped)
-    FV_HIP(run_normext(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
+    FV_HIP(run_normext(c, precision, Xd, vec_ok, N, P, nullptr, n_items, grid2, lse, N,
                        partials, s));
   else
-    FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, xcd_grid(n_items), lse, N,
+    FV_HIP(run_sliced(c, precision, Xd, vec_ok, N, P, nullptr, n_items, grid2, lse, N,
                       partials, s));
   FV_HIP(fv::launch_em(c, partials, n_items, N, var_floor, lse, N, odev, odev + c.K,
                        odev + c.K + KD, lldev, s));

@@ -197,10 +197,23 @@ __device__ __forceinline__ void merge_lse(const float2 (&l)[kMaxLseGroups], int 
 }
 
 // ---- descriptor tile staging ------------------------------------------------------------
+// Every kernel works on centred descriptors x - m0, where m0 is one per-model vector (the
+// weighted mean of the component means, rounded to float; zero past D) whose subtraction the
+// model constants already account for: the encoding is invariant under translating the
+// descriptors and the means together, and centring keeps x, x^2 and the raw moments small
+// when the data sit far from the origin.  stage_centre copies m0 into LDS once per workgroup
+// (and waits for it); the tile loaders subtract it as they write a tile.
+template <int DP, int NT>
+__device__ __forceinline__ void stage_centre(float* cs, const float* __restrict__ cen, int tid) {
+  for (int i = tid; i < DP; i += NT) cs[i] = cen[i];
+  __syncthreads();
+}
+
 // Tile = 32 rows x DP features, fetched as float4 slots into registers by NT threads (thread
 // index `tid`), then written to LDS as [x (DP) | x^2 (DP) | pad 4] per row, or as [x (DP) |
-// pad 4] when SQ is false (the consumer squares on the fly; x * x is rounded the same way).
-// Rows past `valid` and features past D are zero.
+// pad 4] when SQ is false (the consumer squares on the fly; x * x is rounded the same way),
+// x being the centred value.  Rows past `valid` and features past D are fetched as zero (a
+// row past `valid` is staged as -m0 and always gets a zero posterior).
 template <int DP, int NT, bool SQ = true>
 struct TileIO {
   static constexpr int kSlotsPerRow = DP / 4;
@@ -233,14 +246,16 @@ struct TileIO {
     }
   }
 
-  __device__ __forceinline__ static void store(float* xs, const f32x4 (&pre)[kPer], int tid) {
+  // cen: the model centre in LDS (stage_centre); the tile holds x - centre
+  __device__ __forceinline__ static void store(float* xs, const f32x4 (&pre)[kPer],
+                                               const float* cen, int tid) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int idx = tid + q * NT;
       if (idx < kSlots) {
         const int row = idx / kSlotsPerRow;
         const int c4 = (idx % kSlotsPerRow) * 4;
-        const f32x4 v = pre[q];
+        const f32x4 v = pre[q] - *reinterpret_cast<const f32x4*>(cen + c4);
         *reinterpret_cast<f32x4*>(xs + row * XS + c4) = v;
         if (SQ) *reinterpret_cast<f32x4*>(xs + row * XS + DP + c4) = v * v;
       }

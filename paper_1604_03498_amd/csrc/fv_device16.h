@@ -113,14 +113,17 @@ struct TileIO16 {
     }
   }
 
+  // cen: the model centre in LDS (stage_centre); the tile holds x - centre
   template <class T, bool SPLIT>
-  __device__ __forceinline__ static void store(const TL& t, const f32x4 (&pre)[kPer][4], int tid) {
+  __device__ __forceinline__ static void store(const TL& t, const f32x4 (&pre)[kPer][4],
+                                               const float* cen, int tid) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int blk = tid + q * NT;
       if (blk >= TL::kBlocks) continue;
       const int rb = blk % (kTile / 4);
       const int c4 = (blk / (kTile / 4)) * 4;
+      const f32x4 cq = *reinterpret_cast<const f32x4*>(cen + c4);
 #pragma unroll
       for (int sq = 0; sq < 2; ++sq) {  // sq = 0: x, sq = 1: x^2
         const int f0 = c4 + sq * DP;
@@ -129,7 +132,8 @@ struct TileIO16 {
         for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const float v = sq ? pre[q][rr][e] * pre[q][rr][e] : pre[q][rr][e];
+            const float xc = pre[q][rr][e] - cq[e];
+            const float v = sq ? xc * xc : xc;
             T h, l;
             split16<T>(v, h, l);
             hi[rr][e] = bits16<T>(h);
@@ -197,8 +201,10 @@ struct TileIO16Rows {
     }
   }
 
+  // cen: the model centre in LDS (stage_centre); the tile holds x - centre
   template <class T, bool SPLIT>
-  __device__ __forceinline__ static void store(const TL& t, const f32x4 (&pre)[kPer], int tid) {
+  __device__ __forceinline__ static void store(const TL& t, const f32x4 (&pre)[kPer],
+                                               const float* cen, int tid) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int idx = tid + q * NT;
@@ -206,13 +212,14 @@ struct TileIO16Rows {
       const int row = idx % kTile;
       const int c4 = (idx / kTile) * 4;
       const int p = tpos(row);
+      const f32x4 xc = pre[q] - *reinterpret_cast<const f32x4*>(cen + c4);
 #pragma unroll
       for (int sq = 0; sq < 2; ++sq) {
         const int f0 = c4 + sq * DP;
         uint16_t hi[4], lo[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float v = sq ? pre[q][e] * pre[q][e] : pre[q][e];
+          const float v = sq ? xc[e] * xc[e] : xc[e];
           T hh, ll;
           split16<T>(v, hh, ll);
           hi[e] = bits16<T>(hh);

@@ -7,7 +7,8 @@
 //   em_mstep   one thread per (d, k): S0, S1[d], S2[d] summed over the chunk partials in
 //              double, in chunk order; then w = S0 / N, mu = S1 / S0,
 //              var = max(S2 / S0 - mu^2, floor) (a component with S0 = 0 gets w = 0, mu = 0,
-//              var = floor)
+//              var = floor); S1 and S2 are moments of the centred descriptors x - m0, so the
+//              mean returned is S1 / S0 + m0
 //   em_loglik  per row, log2 of sum_k exp2(logit) = M + log2 Z from the first pass's group
 //              normalisers; summed in double per workgroup in a fixed order (grid-stride
 //              rows, then a tree over the workgroup); the caller adds the workgroup sums in
@@ -23,8 +24,8 @@ constexpr int kEmThreads = 256;
 
 __global__ __launch_bounds__(kEmThreads) void em_mstep_kernel(
     const float* __restrict__ partials, int n_items, int K, int D, int DP, int Kp, double n_rows,
-    float var_floor, float* __restrict__ w_out, float* __restrict__ mu_out,
-    float* __restrict__ var_out) {
+    float var_floor, const float* __restrict__ cen, float* __restrict__ w_out,
+    float* __restrict__ mu_out, float* __restrict__ var_out) {
   const int idx = blockIdx.x * kEmThreads + threadIdx.x;
   if (idx >= K * D) return;
   const int k = idx % K;  // consecutive threads: consecutive components (coalesced rows)
@@ -43,7 +44,9 @@ __global__ __launch_bounds__(kEmThreads) void em_mstep_kernel(
     var = s2 / s0 - mu * mu;
     if (!(var >= (double)var_floor)) var = (double)var_floor;
   }
-  mu_out[(size_t)k * D + d] = (float)mu;
+  // the statistics are of the centred descriptors x - m0; the mean goes back by m0 (a
+  // component with S0 = 0 keeps mu = 0)
+  mu_out[(size_t)k * D + d] = (float)(s0 > 0.0 ? mu + (double)cen[d] : 0.0);
   var_out[(size_t)k * D + d] = (float)var;
   if (d == 0) w_out[k] = (float)(s0 / n_rows);
 }
@@ -84,7 +87,7 @@ hipError_t launch_em(const Consts& c, const float* partials, int n_items, int64_
   const int KD = c.K * c.D;
   hipLaunchKernelGGL(em_mstep_kernel, dim3((KD + kEmThreads - 1) / kEmThreads), dim3(kEmThreads),
                      0, stream, partials, n_items, c.K, c.D, c.DP, c.Kp, (double)N, var_floor,
-                     w_out, mu_out, var_out);
+                     c.cen, w_out, mu_out, var_out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(em_loglik_kernel, dim3(em_loglik_blocks(N)), dim3(kEmThreads), 0, stream,

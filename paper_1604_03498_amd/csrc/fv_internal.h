@@ -17,6 +17,9 @@ constexpr int kMaxWaves = 8;      // 8 waves x 32 components = 256 components pe
 constexpr int kFusedMaxK = kCompsPerWave * kMaxWaves;  // fused single-pass kernel
 constexpr int kMaxK = 1024;                               // two-pass path
 constexpr int kMaxD = 96;
+#ifndef FV_NOALLOC_SCRATCH_BYTES
+#define FV_NOALLOC_SCRATCH_BYTES (64u << 20)
+#endif
 // The paper's posterior threshold (Algorithm 1): with it on, a term enters the statistics only
 // if its posterior exceeds kTau.
 constexpr float kTau = 1e-6f;
@@ -41,8 +44,12 @@ struct Consts {
   const uint16_t* Ah_lo;
   // log2(e)-scaled offsets [Kp]; padded components get -1e30 (posterior exactly 0)
   const float* c32;
+  // model centre m0 [DP] f32 (zero past D): the kernels stage every descriptor as x - m0, and
+  // every other constant here is computed for the centred means mu - m0 (the encoding is
+  // invariant under translating descriptors and means together)
+  const float* cen;
   // finalize constants, double, [K*D] or [K]
-  const double* mu64;
+  const double* mu64;    // centred means mu - m0
   const double* isd64;   // 1/sigma
   const double* ivar64;  // 1/sigma^2
   const double* cu64;    // 1/sqrt(w)
@@ -131,6 +138,16 @@ hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* 
 
 // Blocks per frame of the assembly step (size of normpart per frame).
 int finalize_blocks(const Consts& c);
+
+// fv_encode with every intermediate in the caller's device scratch (scratch_bytes at scratch):
+// X and out in device memory (both FV_X_DEVICE and FV_OUT_DEVICE set), no allocation, no
+// graph, no timing events; FV_E_UNSUPPORTED when the frame's intermediates do not fit.
+int encode_with_scratch(const struct ::fv_gmm* gmm, const float* X, int64_t N, float* out,
+                        int precision, unsigned flags, void* hip_stream, char* scratch,
+                        size_t scratch_bytes);
+// hipSetDevice, and a HIP error turned into an FV_E_* code (recorded for fv_last_device_error).
+int set_device(int device);
+int device_error(hipError_t e);
 
 // Device bytes one fv_encode_batch call needs for frames of the given sizes (workspace plus
 // device-resident X and out), used by the server's admission control.

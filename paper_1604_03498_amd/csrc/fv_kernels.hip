@@ -37,8 +37,9 @@ template <int DP, int W, bool LSE, bool TH, bool GOUT = false>
 __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float* __restrict__ A32,
-    const float* __restrict__ c32, int Kp, float* __restrict__ partials,
-    float2* __restrict__ lse, int64_t lse_stride, float* __restrict__ gout, int64_t gstride) {
+    const float* __restrict__ c32, const float* __restrict__ cen, int Kp,
+    float* __restrict__ partials, float2* __restrict__ lse, int64_t lse_stride,
+    float* __restrict__ gout, int64_t gstride) {
   constexpr int NT = 64 * W;
   constexpr int NB = 2 * DP / 32;  // 32-feature output blocks of the statistics contraction
   // At 8 waves (two per SIMD, 256 registers each) the statistics kernel cannot also hold its
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
   __shared__ __attribute__((aligned(16))) float xm[kTile * W];   // [row][wave] maxima
   __shared__ __attribute__((aligned(16))) float xsum[kTile * W]; // [row][wave] sums
   __shared__ __attribute__((aligned(16))) float loc[W][kTile];   // wave-private scratch
+  __shared__ __attribute__((aligned(16))) float cs[DP];          // model centre
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -69,6 +71,7 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
     load_areg<DP>(areg, A32, comp / kCompsPerWave, lane);
   const float cval = c32[comp];
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
+  stage_centre<DP, NT>(cs, cen, tid);
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     int64_t row0;
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
 
     f32x4 pre[IO::kPer];
     IO::fetch(pre, X, D, vec_ok != 0, row0, nrows < kTile ? nrows : kTile, tid);
-    IO::store(xs[0], pre, tid);
+    IO::store(xs[0], pre, cs, tid);
     __syncthreads();
 
     for (int t = 0; t < ntiles; ++t) {
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
           stats_f32<DP, TH>(xb, h, j, e, acc);
       }
 
-      if (has_next) IO::store(xs[buf ^ 1], pre, tid);
+      if (has_next) IO::store(xs[buf ^ 1], pre, cs, tid);
       __syncthreads();
     }
 
@@ -194,8 +197,8 @@ template <int DP, int W, bool TH>
 __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float2* __restrict__ lse, int G,
-    int64_t lse_stride, const float* __restrict__ A32, const float* __restrict__ c32, int Kp,
-    float* __restrict__ partials) {
+    int64_t lse_stride, const float* __restrict__ A32, const float* __restrict__ c32,
+    const float* __restrict__ cen, int Kp, float* __restrict__ partials) {
   constexpr int NT = 64 * W;
   constexpr int NB = 2 * DP / 32;
   using IO = TileIO<DP, NT>;
@@ -203,6 +206,7 @@ __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
 
   __shared__ __attribute__((aligned(16))) float xs[2][kTile * XS];
   __shared__ __attribute__((aligned(16))) float nrm[2][2 * kTile];  // per row: M, log2 Z
+  __shared__ __attribute__((aligned(16))) float cs[DP];             // model centre
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -215,6 +219,7 @@ __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
   load_areg<DP>(areg, A32, comp / kCompsPerWave, lane);
   const float cval = c32[comp];
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
+  stage_centre<DP, NT>(cs, cen, tid);
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     int64_t row0;
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
       if (tid < kTile) fetch_lse(lv, lse, G, lse_stride, row0 + (int64_t)t * kTile + tid, tid < valid_of(t));
     };
     auto stage = [&](int buf, int t) {
-      IO::store(xs[buf], pre, tid);
+      IO::store(xs[buf], pre, cs, tid);
       if (tid < kTile) {
         float M = 0.f, L2Z = INFINITY;  // rows past the tile end get gamma = 0
         if (tid < valid_of(t)) merge_lse(lv, G, M, L2Z);
@@ -316,11 +321,11 @@ hipError_t launch_normext_dp(const Consts& c, const float* X, bool vec_ok, int64
   if (c.thresh)
     hipLaunchKernelGGL((normext_f32_kernel<DP, W, true>), grd, dim3(64 * W), 0, stream, X, c.D,
                        vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c), lse_stride,
-                       c.A32, c.c32, c.Kp, partials);
+                       c.A32, c.c32, c.cen, c.Kp, partials);
   else
     hipLaunchKernelGGL((normext_f32_kernel<DP, W, false>), grd, dim3(64 * W), 0, stream, X, c.D,
                        vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c), lse_stride,
-                       c.A32, c.c32, c.Kp, partials);
+                       c.A32, c.c32, c.cen, c.Kp, partials);
   return hipGetLastError();
 }
 
@@ -348,7 +353,7 @@ hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N,
     if (c.thresh) {
       hipLaunchKernelGGL((fused_f32_kernel<DP, W, false, true>), dim3(grid, groups), dim3(64 * W),
                          0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32,
-                         c.Kp, partials, lse, lse_stride, nullptr, 0);
+                         c.cen, c.Kp, partials, lse, lse_stride, nullptr, 0);
       return hipGetLastError();
     }
   } else {
@@ -358,7 +363,7 @@ hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N,
         if (groups != 1) return hipErrorInvalidValue;
         hipLaunchKernelGGL((fused_f32_kernel<DP, W, true, false, true>), dim3(grid, 1),
                            dim3(64 * W), 0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items,
-                           c.A32, c.c32, c.Kp, partials, lse, lse_stride, gout, gstride);
+                           c.A32, c.c32, c.cen, c.Kp, partials, lse, lse_stride, gout, gstride);
         return hipGetLastError();
       } else {
         return hipErrorInvalidValue;
@@ -366,8 +371,8 @@ hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N,
     }
   }
   hipLaunchKernelGGL((fused_f32_kernel<DP, W, LSE, false>), dim3(grid, groups), dim3(64 * W), 0,
-                     stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32, c.Kp,
-                     partials, lse, lse_stride, nullptr, 0);
+                     stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32, c.cen,
+                     c.Kp, partials, lse, lse_stride, nullptr, 0);
   return hipGetLastError();
 }
 

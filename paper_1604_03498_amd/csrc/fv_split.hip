@@ -36,14 +36,16 @@ template <int DP, int NW, bool TH, bool GIN>
 __global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float2* __restrict__ lse, int G,
-    int64_t lse_stride, const float* __restrict__ A32, const float* __restrict__ c32, int Kp,
-    const float* __restrict__ gin, int64_t gstride, float* __restrict__ partials) {
+    int64_t lse_stride, const float* __restrict__ A32, const float* __restrict__ c32,
+    const float* __restrict__ cen, int Kp, const float* __restrict__ gin, int64_t gstride,
+    float* __restrict__ partials) {
   constexpr int NB = 2 * DP / 32;
   using IO = TileIO<DP, 64>;
   constexpr int XS = IO::XS;
 
   __shared__ __attribute__((aligned(16))) float xs[NW][kTile * XS];
   __shared__ __attribute__((aligned(16))) float ls[NW][kTile * 2];
+  __shared__ __attribute__((aligned(16))) float cs[DP];  // model centre
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -62,6 +64,7 @@ __global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
   float* xw = xs[w];
   float* lw = ls[w];
+  stage_centre<DP, 64 * NW>(cs, cen, tid);
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     int64_t row0;
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(64 * NW, 2) void sliced_f32_kernel(
         lw[2 * lane] = M;
         lw[2 * lane + 1] = L2Z;
       }
-      IO::store(xw, pre, lane);
+      IO::store(xw, pre, cs, lane);
       wave_sync();
 
       if constexpr (!GIN) {
@@ -187,7 +190,7 @@ void launch_sliced_k(const Consts& c, const float* X, bool vec_ok, int64_t N, in
   constexpr int NW = slice_waves(DP);
   hipLaunchKernelGGL((sliced_f32_kernel<DP, NW, TH, GIN>), dim3(grid, c.Kp / kCompsPerWave),
                      dim3(64 * NW), 0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, lse,
-                     lse_groups(c), lse_stride, c.A32, c.c32, c.Kp, gin, gstride, partials);
+                     lse_groups(c), lse_stride, c.A32, c.c32, c.cen, c.Kp, gin, gstride, partials);
 }
 
 template <int DP>
