@@ -14,5 +14,5 @@ D of 64-82, ~10^4 descriptors per 320x240 frame).
 """
 from .gen import (  # noqa: F401
     Gmm, gmm, frame, batch_sizes, batch_frames, serving_plan, workload, WORKLOADS,
-    array_sha256, Pca, pca, raw_frame, raw_batch,
+    array_sha256, Pca, pca, raw_frame, raw_batch, image, images,
 )

@@ -18,6 +18,11 @@
   D dimensions; n ~ N(0, noise^2)^{N x n_sift} from default_rng(seed + 1_000_003);
   sift = sift_mean + y[:, :m] Q^T + n (I - Q Q^T); raw = [sift, y[:, m:]], cast to float32.
   So A (raw - mean) = y up to the float32 rounding of raw.
+* image(H, W, seed): a grayscale video-frame stand-in in [0, 1]: rng = default_rng(seed);
+  a smooth field sum_{q<6} a_q sin(2 pi (f_q . (x, y)) + p_q) with a_q ~ U[0.05, 0.2],
+  |f_q| ~ U[1/64, 1/8] cycles per pixel at a uniform angle, p_q ~ U[0, 2 pi); plus 12
+  axis-aligned rectangles (corners uniform in the frame) adding U[-0.3, 0.3] each; plus
+  N(0, 0.03^2) pixel noise; then mapped affinely onto [0, 1] (no clipping), cast to float32.
 * serving_plan(...): 16 streams, Poisson arrivals at a rate per stream, resolutions
   assigned round-robin from 320x240 .. 640x480, N = 8000 * area / (320*240).
 """
@@ -131,6 +136,32 @@ def batch_frames(g: Gmm, sizes, seed0: int = 200, outlier_frac: float = 0.05):
     offsets[1:] = np.cumsum([f.shape[0] for f in frames])
     X = np.concatenate(frames, axis=0) if frames else np.zeros((0, g.D), np.float32)
     return np.ascontiguousarray(X), offsets
+
+
+def image(H: int, W: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    yy, xx = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64),
+                         indexing="ij")
+    f = np.zeros((H, W))
+    for _ in range(6):
+        a = rng.uniform(0.05, 0.2)
+        fr = rng.uniform(1.0 / 64, 1.0 / 8)
+        ang = rng.uniform(0.0, 2 * np.pi)
+        ph = rng.uniform(0.0, 2 * np.pi)
+        f += a * np.sin(2 * np.pi * fr * (np.cos(ang) * xx + np.sin(ang) * yy) + ph)
+    for _ in range(12):
+        x0, x1 = np.sort(rng.integers(0, W + 1, 2))
+        y0, y1 = np.sort(rng.integers(0, H + 1, 2))
+        f[y0:y1, x0:x1] += rng.uniform(-0.3, 0.3)
+    f += rng.standard_normal((H, W)) * 0.03
+    lo, hi = f.min(), f.max()
+    f = (f - lo) / (hi - lo) if hi > lo else np.zeros_like(f)
+    return np.ascontiguousarray(f.astype(np.float32))
+
+
+def images(n: int, H: int, W: int, seed0: int = 0) -> np.ndarray:
+    """n frames, frame i drawn by image(H, W, seed0 + i): [n, H, W] float32."""
+    return np.ascontiguousarray(np.stack([image(H, W, seed0 + i) for i in range(n)]))
 
 
 RESOLUTIONS = ((320, 240), (400, 300), (480, 360), (560, 420), (640, 480))

@@ -210,6 +210,60 @@ int fv_encode_batch_projected(const fv_gmm* gmm, const fv_pca* pca, const float*
                               const int64_t* offsets, int B, float* out, int precision,
                               unsigned flags, void* hip_stream);
 
+/* ---- dense-SIFT front end ----------------------------------------------------------------
+ * Flat-window dense SIFT on the GPU (Sec. 3.1: per scale of the image, the gradient of every
+ * pixel falls into 8 orientation bins, a triangular convolution follows, and each descriptor
+ * holds the 8 values of 4 x 4 spatial bins, taken at a stride; Sec. 3.2: the triangular filter
+ * is applied once along each image dimension, and the second convolution only where a
+ * descriptor reads it; Sec. 4: stride 4 and scales from 2 (or sqrt 2) down to 1/8).  The paper
+ * leaves the resampling, gradient, binning, window and normalisation unstated; this library
+ * computes, per scale s of an H x W grayscale image (float32, row-major):
+ *   resize       Hs = round(s H), Ws = round(s W) (ties to even; the image itself at s = 1),
+ *                bilinear at the source point ((x + 1/2) / s - 1/2, (y + 1/2) / s - 1/2)
+ *                clamped to the image
+ *   gradient     central differences (I[x+1] - I[x-1]) / 2, one-sided at the first and last
+ *                column (row)
+ *   binning      t = 8 atan2(gy, gx) / (2 pi) in [0, 8); magnitude shared by bins floor(t)
+ *                (weight 1 - frac t) and floor(t) + 1 mod 8 (weight frac t)
+ *   window       w(d) = (B - |d|) / B^2 for |d| < B (B = `bin`), zero outside the image,
+ *                along y, then along x
+ *   sampling     descriptor (x0, y0) = (a step, b step), x0 + 3B <= Ws - 1, y0 + 3B <= Hs - 1;
+ *                spatial bin (i, j) reads the filtered maps at (x0 + i B, y0 + j B); value
+ *                (4 j + i) * 8 + o
+ *   normalise    L2, clamp at 0.2, L2 (a zero vector stays zero)
+ *   row          the 128 values, then ((x0 + 1.5 B + 1/2) / Ws - 1/2, (y0 + 1.5 B + 1/2) / Hs
+ *                - 1/2): FV_DSIFT_DIM = 130 floats, rows of scale 0 first, then scale 1, ...
+ * Arithmetic is float32 (resampling coordinates in double); results agree with a float64
+ * evaluation to rounding.
+ *   scales       n_scales factors (1..16, finite and > 0), or NULL for the n_scales (1..9)
+ *                smallest of 2, sqrt 2, 1, ..., 1/8 (8: the paper's 8-scale setting)
+ *   bin, step    1 <= bin <= 16, step >= 1
+ * Limits: H, W <= 16384, scaled sides <= 32768 (FV_E_UNSUPPORTED beyond).
+ */
+#define FV_DSIFT_DIM 130
+
+/* Descriptors one image yields (*n_rows; 0 when no scale fits a descriptor).  Errors:
+ * FV_E_INVAL (bad sizes, scales, bin or step), FV_E_UNSUPPORTED. */
+int fv_dsift_rows(int H, int W, int n_scales, const double* scales, int bin, int step,
+                  int64_t* n_rows);
+
+/* Extract the descriptors of n_images images [n_images x H x W] (FV_X_DEVICE: device memory,
+ * else host) into rows [n_images x n_rows x FV_DSIFT_DIM] (FV_OUT_DEVICE: device memory, 8-byte
+ * aligned, else host) on `device`, stream `hip_stream`; FV_ASYNC as for fv_encode.  The caller
+ * owns both arrays.  Errors: FV_E_INVAL (null pointers, bad sizes or flags),
+ * FV_E_UNSUPPORTED (n_images > 65535 or the limits above), FV_E_NOMEM, FV_E_DEVICE. */
+int fv_dsift(const float* images, int n_images, int H, int W, int n_scales,
+             const double* scales, int bin, int step, float* rows, unsigned flags, int device,
+             void* hip_stream);
+
+/* Fisher vector of each image: fv_dsift (into the library's scratch), the projection `pca`
+ * (Din = FV_DSIFT_DIM, D = the GMM's D), then the batched encode with image n as frame n;
+ * out [n_images x 2KD].  Images on the host (copied in) or device (FV_X_DEVICE); out per
+ * FV_OUT_DEVICE; other flags and errors as fv_encode_batch and fv_dsift. */
+int fv_encode_images(const fv_gmm* gmm, const fv_pca* pca, const float* images, int n_images,
+                     int H, int W, int n_scales, const double* scales, int bin, int step,
+                     float* out, int precision, unsigned flags, void* hip_stream);
+
 /* ---- training step -------------------------------------------------------------------- */
 /*
  * One EM iteration for the GMM (the model the encoder uses is trained beforehand, Sec. 3.1).

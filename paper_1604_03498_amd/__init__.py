@@ -12,5 +12,6 @@ from .fv import (  # noqa: F401
     NO_POWER_NORM, NO_L2_NORM, ASYNC, THRESHOLD, THRESHOLD_TAU, EXPORTED_SYMBOLS, EXEC_HIP,
     EXEC_FAKE, Server, ServerConfig,
     server_config, set_tuning, get_tuning, Tuning, Pca, pca_load, project, encode_projected,
-    encode_batch_projected, em_step, em_fit, stream_release,
+    encode_batch_projected, em_step, em_fit, stream_release, DSIFT_DIM, dsift_rows, dsift,
+    encode_images,
 )

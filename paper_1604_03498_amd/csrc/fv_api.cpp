@@ -580,13 +580,17 @@ int fv_stream_release(int device, void* hip_stream) {
   {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto it = g_ws.find({device, s});
-    if (it == g_ws.end()) return FV_OK;
-    ws = std::move(it->second);
-    g_ws.erase(it);
+    if (it != g_ws.end()) {
+      ws = std::move(it->second);
+      g_ws.erase(it);
+    }
   }
-  if (!ws) return FV_OK;
+  const bool front = fv::dsift_in_use(device, s);
+  if (!ws && !front) return FV_OK;  // a pair never used: no device call at all
   DeviceGuard g(device);
   if (g.status() != hipSuccess) return hip_fail(g.status());
+  const int rc_front = fv::dsift_release(device, s);
+  if (!ws) return rc_front;
   std::lock_guard<std::mutex> lk(ws->mu);
   int rc = FV_OK;
   hipError_t e = hipStreamSynchronize(s);
@@ -596,7 +600,7 @@ int fv_stream_release(int device, void* hip_stream) {
   if (ws->pinned && (e = hipHostFree(ws->pinned)) != hipSuccess) rc = hip_fail(e);
   if (ws->pin_done) (void)hipEventDestroy(ws->pin_done);
   ws->dev = ws->pinned = nullptr;
-  return rc;
+  return rc != FV_OK ? rc : rc_front;
 }
 
 int fv_gmm_load(int K, int D, const float* priors, const float* means, const float* variances,
@@ -1185,6 +1189,36 @@ int fv_encode_batch_projected(const fv_gmm* gmm, const fv_pca* pca, const float*
                               unsigned flags, void* hip_stream) {
   if (!pca) return FV_E_INVAL;
   return encode_batch_impl(gmm, pca, X, offsets, B, out, precision, flags, hip_stream);
+}
+
+int fv_encode_images(const fv_gmm* gmm, const fv_pca* pca, const float* images, int n_images,
+                     int H, int W, int n_scales, const double* scales, int bin, int step,
+                     float* out, int precision, unsigned flags, void* hip_stream) {
+  if (!gmm || !pca || n_images < 0) return FV_E_INVAL;
+  if (flags & ~kAllFlags) return FV_E_INVAL;
+  if (pca->Din != fv::kDsiftDim || pca->D != gmm->D || pca->device != gmm->device)
+    return FV_E_INVAL;
+  if (const int fs = fv_form_status(gmm, precision)) return fs;
+  const fv::DsiftPlan* p = nullptr;
+  int rc = fv::dsift_plan(H, W, n_scales, scales, bin, step, &p);
+  if (rc) return rc;
+  if (n_images == 0) return FV_OK;
+  if (!images || !out) return FV_E_INVAL;
+  if ((size_t)n_images * (size_t)p->ndesc * fv::kDsiftDim * 4 > ((size_t)1 << 40))
+    return FV_E_UNSUPPORTED;
+  DeviceGuard g(gmm->device);
+  if (g.status() != hipSuccess) return hip_fail(g.status());
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  // descriptors of every image into the front end's workspace, then the projected batch
+  // encode of the images' rows (one frame per image) on the same stream
+  float* rows = nullptr;
+  rc = fv::dsift_enqueue(*p, gmm->device, s, images, (flags & FV_X_DEVICE) != 0, n_images,
+                         nullptr, &rows);
+  if (rc) return rc;
+  std::vector<int64_t> offsets((size_t)n_images + 1);
+  for (int b = 0; b <= n_images; ++b) offsets[(size_t)b] = (int64_t)b * p->ndesc;
+  return encode_batch_impl(gmm, pca, rows, offsets.data(), n_images, out, precision,
+                           flags | FV_X_DEVICE, hip_stream);
 }
 
 int fv_pca_load(int Din, int D, const float* A, const float* mean, int device, fv_pca** out) {

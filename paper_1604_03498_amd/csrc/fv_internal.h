@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "fv.h"
 
 struct fv_gmm;
@@ -199,6 +201,59 @@ int em_loglik_blocks(int64_t N);
 hipError_t launch_em(const Consts& c, const float* partials, int n_items, int64_t N,
                      float var_floor, const float2* lse, int64_t lse_stride, float* w_out,
                      float* mu_out, float* var_out, double* ll_part, hipStream_t stream);
+
+// ---- dense-SIFT front end (fv_dsift.hip, fv_dsift_host.cpp) -------------------------------
+constexpr int kDsiftDim = 130;  // 128 SIFT values + the centre's normalised x and y
+constexpr int kDsiftMaxScales = 16;
+constexpr int kDsiftMaxBin = 16;
+constexpr int kDsiftMaxSide = 16384;   // source image side
+constexpr int kDsiftMaxScaled = 32768; // scaled image side
+
+// One scale of the extraction (scales without descriptors are left out of the table).  The
+// filtered maps are evaluated at the nR needed rows and nC needed columns (sorted lists at
+// lists[row0..], lists[col0..]); descriptor (a, b) of the nx x ny grid reads spatial bin
+// (i, j) at needed column lists[cidx0 + 4a + i] and needed row lists[ridx0 + 4b + j].
+struct DsiftScale {
+  double s;          // scale factor (1: the source image itself)
+  int Hs, Ws;        // scaled image size
+  int nx, ny;        // descriptor grid
+  int nR, nC;        // needed rows and columns
+  int ntx;           // column tiles of the filter kernel
+  int blk0;          // first filter workgroup of this scale (per image)
+  int row0, col0, ridx0, cidx0;
+  int pad;
+  int64_t desc0;     // first descriptor of this scale (per image)
+  int64_t fxy0;      // first filtered value of this scale (per image): [nR][nC][8] floats
+};
+
+struct DsiftPlan {
+  int H = 0, W = 0, B = 0, S = 0, nsc = 0;
+  int64_t ndesc = 0;       // descriptors per image
+  int64_t fxy_floats = 0;  // filtered values per image
+  int64_t nblk = 0;        // filter workgroups per image
+  std::vector<DsiftScale> scales;
+  std::vector<int> lists;
+  std::vector<double> factors;  // the requested scale factors (cache key)
+};
+
+// LDS bytes of one filter workgroup and its output columns per tile, for bin size B.
+size_t dsift_filter_lds_bytes(int B);
+int dsift_filter_tile_cols(int B);
+// Both kernels of the front end on `stream`: images [n_images][H][W] -> rows
+// [n_images][ndesc][kDsiftDim]; fxy holds n_images * fxy_floats floats of scratch.
+hipError_t launch_dsift(const DsiftPlan& p, const DsiftScale* dscales, const int* dlists,
+                        const float* images, int n_images, float* fxy, float* rows,
+                        hipStream_t stream);
+// Host side (fv_dsift_host.cpp): the validated, cached plan of a geometry (FV_E_INVAL /
+// FV_E_UNSUPPORTED for bad or oversized arguments); enqueueing on stream s of `device`
+// (current) with images in device memory or, when images_dev is false, host memory copied
+// into the stream's workspace; rows == nullptr puts the rows into the workspace and returns
+// them in *rows_ws (valid until the next call on the stream).
+int dsift_plan(int H, int W, int nsc, const double* scales, int B, int S, const DsiftPlan** out);
+int dsift_enqueue(const DsiftPlan& p, int device, hipStream_t s, const float* images,
+                  bool images_dev, int n_images, float* rows, float** rows_ws);
+int dsift_release(int device, hipStream_t s);
+bool dsift_in_use(int device, hipStream_t s);  // the pair holds a front-end workspace
 
 }  // namespace fv
 

@@ -17,6 +17,7 @@ E_AGAIN, E_NOTFOUND, E_TIMEOUT, E_UNSUPPORTED = -5, -6, -7, -8
 PREC_FP32, PREC_BF16_SPLIT, PREC_FP16_SPLIT, PREC_BF16 = 0, 1, 2, 3
 X_DEVICE, OUT_DEVICE, NO_POWER_NORM, NO_L2_NORM, ASYNC, THRESHOLD = 1, 2, 4, 8, 16, 32
 THRESHOLD_TAU = 1e-6  # posteriors at or below it are left out under THRESHOLD
+DSIFT_DIM = 130  # dense-SIFT row: 128 values + the centre's normalised x and y
 
 EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "fv_encode",
                     "fv_encode_batch", "fv_gmm_set_tuning", "fv_gmm_get_tuning",
@@ -26,7 +27,7 @@ EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "f
                     "fv_server_get_stats", "fv_strerror", "fv_last_device_error",
                     "fv_pca_load", "fv_pca_free", "fv_pca_info", "fv_project",
                     "fv_encode_projected", "fv_encode_batch_projected", "fv_em_step",
-                    "fv_stream_release")
+                    "fv_stream_release", "fv_dsift_rows", "fv_dsift", "fv_encode_images")
 EXEC_HIP, EXEC_FAKE = 0, 1
 
 
@@ -127,9 +128,13 @@ def load():
     lib.fv_em_step.argtypes = [vp, vp, i64, i32, ctypes.c_float, u32, vp, vp, vp, vp,
                                ctypes.POINTER(ctypes.c_double)]
     lib.fv_stream_release.argtypes = [i32, vp]
+    lib.fv_dsift_rows.argtypes = [i32, i32, i32, vp, i32, i32, ctypes.POINTER(i64)]
+    lib.fv_dsift.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp, u32, i32, vp]
+    lib.fv_encode_images.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, i32, i32, vp, i32, u32,
+                                     vp]
     for f in (lib.fv_pca_load, lib.fv_pca_free, lib.fv_pca_info, lib.fv_project,
               lib.fv_encode_projected, lib.fv_encode_batch_projected, lib.fv_em_step,
-              lib.fv_stream_release):
+              lib.fv_stream_release, lib.fv_dsift_rows, lib.fv_dsift, lib.fv_encode_images):
         f.restype = i32
     for f in (lib.fv_gmm_load, lib.fv_gmm_free, lib.fv_gmm_info, lib.fv_encode,
               lib.fv_encode_batch, lib.fv_kernel_timing, lib.fv_kernel_timing_read,
@@ -435,6 +440,93 @@ def encode_batch_projected(g: Gmm, p: Pca, X, offsets, out=None, precision: int 
                                             ctypes.c_void_p(xp), ctypes.c_void_p(off.ctypes.data),
                                             int(B), ctypes.c_void_p(op), int(precision), f,
                                             ctypes.c_void_p(s)), "fv_encode_batch_projected")
+    return out
+
+
+def _scales_arg(scales, n_scales):
+    """(count, pointer, keepalive) of a scale list; None asks for the n_scales smallest of the
+    paper's nine scales (2 down to 1/8)."""
+    if scales is None:
+        return int(n_scales), None, None
+    sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64).reshape(-1))
+    return int(sc.size), sc.ctypes.data, sc
+
+
+def dsift_rows(H: int, W: int, scales=None, n_scales: int = 8, bin: int = 4,
+               step: int = 4) -> int:
+    """fv_dsift_rows: descriptors per H x W image."""
+    n, sp, _keep = _scales_arg(scales, n_scales)
+    r = ctypes.c_int64()
+    _check(load().fv_dsift_rows(int(H), int(W), n, ctypes.c_void_p(sp), int(bin), int(step),
+                                ctypes.byref(r)), "fv_dsift_rows")
+    return int(r.value)
+
+
+def _marshal_images(images, device: int):
+    """(pointer, n_images, H, W, is_device, keepalive) of [n, H, W] (or [H, W]) float32."""
+    if _is_torch(images):
+        import torch
+        if images.dtype != torch.float32 or images.dim() not in (2, 3) or not images.is_contiguous():
+            raise ValueError("images must be a contiguous float32 [n, H, W] or [H, W] tensor")
+        im = images.unsqueeze(0) if images.dim() == 2 else images
+        if im.is_cuda:
+            if im.device.index != device:
+                raise ValueError("images are on another device")
+            return im.data_ptr(), im.shape[0], im.shape[1], im.shape[2], True, im
+        a = im.numpy()
+        return a.ctypes.data, a.shape[0], a.shape[1], a.shape[2], False, a
+    a = _host_f32(images)
+    if a.ndim == 2:
+        a = a[None]
+    if a.ndim != 3:
+        raise ValueError("images must be [n, H, W] or [H, W]")
+    return a.ctypes.data, a.shape[0], a.shape[1], a.shape[2], False, a
+
+
+def dsift(images, scales=None, n_scales: int = 8, bin: int = 4, step: int = 4, device: int = 0,
+          out=None, stream=None):
+    """fv_dsift: [n, H, W] (or [H, W]) float32 images -> [n, rows, 130] descriptors (a device
+    tensor for device images, a host array for host images)."""
+    ip, n, H, W, idev, _ki = _marshal_images(images, device)
+    ns, sp, _ks = _scales_arg(scales, n_scales)
+    rows = dsift_rows(H, W, scales, n_scales, bin, step)
+    shape = (n, rows, DSIFT_DIM)
+    if out is None:
+        if idev:
+            import torch
+            out = torch.empty(shape, dtype=torch.float32, device=f"cuda:{device}")
+        else:
+            out = np.empty(shape, dtype=np.float32)
+    if _is_torch(out):
+        if tuple(out.shape) != shape or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float32 tensor of shape {shape}")
+        op, odev = (out.data_ptr(), True) if out.is_cuda else (out.numpy().ctypes.data, False)
+    else:
+        if out.dtype != np.float32 or out.shape != shape or not out.flags.c_contiguous:
+            raise ValueError(f"out must be a contiguous float32 array of shape {shape}")
+        op, odev = out.ctypes.data, False
+    f = (X_DEVICE if idev else 0) | (OUT_DEVICE if odev else 0)
+    s = _stream_handle(stream, device) if (idev or odev or stream is not None) else 0
+    _check(load().fv_dsift(ctypes.c_void_p(ip), int(n), int(H), int(W), ns, ctypes.c_void_p(sp),
+                           int(bin), int(step), ctypes.c_void_p(op), f, int(device),
+                           ctypes.c_void_p(s)), "fv_dsift")
+    return out
+
+
+def encode_images(g: Gmm, p: Pca, images, scales=None, n_scales: int = 8, bin: int = 4,
+                  step: int = 4, out=None, precision: int = PREC_FP32, flags: int = 0,
+                  stream=None):
+    """fv_encode_images: one Fisher vector per image, [n, 2KD]."""
+    ip, n, H, W, idev, _ki = _marshal_images(images, g.device)
+    ns, sp, _ks = _scales_arg(scales, n_scales)
+    out, op, odev = _marshal_out(g, out, n, idev)
+    f = int(flags) & ~(X_DEVICE | OUT_DEVICE)
+    f |= (X_DEVICE if idev else 0) | (OUT_DEVICE if odev else 0)
+    s = _stream_handle(stream, g.device) if (idev or odev or stream is not None) else 0
+    _check(load().fv_encode_images(ctypes.c_void_p(g.handle), ctypes.c_void_p(p.handle),
+                                   ctypes.c_void_p(ip), int(n), int(H), int(W), ns,
+                                   ctypes.c_void_p(sp), int(bin), int(step), ctypes.c_void_p(op),
+                                   int(precision), f, ctypes.c_void_p(s)), "fv_encode_images")
     return out
 
 

@@ -56,6 +56,22 @@ static void validation() {
   CHECK(fv_pca_load(2, 2, Anan, m, 0, &p) == FV_E_INVAL);
   CHECK(fv_pca_free(nullptr) == FV_OK);
   CHECK(fv_stream_release(0, nullptr) == FV_OK);  // never used: nothing cached
+  // dense-SIFT plan and argument checks (host only)
+  int64_t nr = -1;
+  const double sc[2] = {1.0, 0.5}, bad_sc[1] = {-1.0};
+  CHECK(fv_dsift_rows(240, 320, 8, nullptr, 4, 4, &nr) == FV_OK && nr == 17479);
+  CHECK(fv_dsift_rows(241, 321, 2, sc, 4, 4, &nr) == FV_OK && nr > 0);
+  CHECK(fv_dsift_rows(10, 10, 1, sc, 4, 4, &nr) == FV_OK && nr == 0);
+  CHECK(fv_dsift_rows(0, 10, 1, sc, 4, 4, &nr) == FV_E_INVAL);
+  CHECK(fv_dsift_rows(10, 10, 1, bad_sc, 4, 4, &nr) == FV_E_INVAL);
+  CHECK(fv_dsift_rows(10, 10, 10, nullptr, 4, 4, &nr) == FV_E_INVAL);
+  CHECK(fv_dsift_rows(10, 10, 1, sc, 17, 4, &nr) == FV_E_UNSUPPORTED);
+  CHECK(fv_dsift_rows(10, 10, 1, sc, 4, 4, nullptr) == FV_E_INVAL);
+  CHECK(fv_dsift(nullptr, 0, 64, 64, 1, sc, 4, 4, nullptr, 0, 0, nullptr) == FV_OK);
+  CHECK(fv_dsift(nullptr, -1, 64, 64, 1, sc, 4, 4, nullptr, 0, 0, nullptr) == FV_E_INVAL);
+  CHECK(fv_dsift(nullptr, 1, 64, 64, 1, sc, 4, 4, nullptr, 64u, 0, nullptr) == FV_E_INVAL);
+  CHECK(fv_encode_images(nullptr, nullptr, nullptr, 1, 64, 64, 1, sc, 4, 4, out, 0, 0, nullptr) ==
+        FV_E_INVAL);
   for (int code = -9; code <= 1; ++code) CHECK(fv_strerror(code) != nullptr);
 }
 
