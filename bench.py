@@ -176,6 +176,8 @@ def parse():
     ap.add_argument("--no-em", action="store_true", help="skip the EM-step measurement")
     ap.add_argument("--no-projection", action="store_true",
                     help="skip the projection-prologue measurements")
+    ap.add_argument("--no-dsift", action="store_true",
+                    help="skip the dense-SIFT front end measurement")
     ap.add_argument("--no-paper-mode", action="store_true",
                     help="skip the posterior-threshold (paper mode) measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -690,6 +692,49 @@ def main():
             fv.set_tuning(hb)
         hp.free()
 
+    # Dense-SIFT front end: synthetic 320x240 grayscale frames, the 8 scales sqrt 2 .. 1/8, bin
+    # 4, stride 4 (the paper's setting); descriptors alone (HBM-bound: the image in, 520 bytes
+    # per 130-value row out), and image -> Fisher vector (dense SIFT, projection 130 -> 64,
+    # batched encode), for one frame and a batch of 64
+    dsift = {}
+    if not a.no_dsift:
+        Hi, Wi, nimg = 240, 320, 64
+        imgs = torch.from_numpy(fvsynth.images(nimg, Hi, Wi, 900)).to(dev)
+        rows_per = fv.dsift_rows(Hi, Wi)
+        rows_out = torch.empty(nimg, rows_per, fv.DSIFT_DIM, dtype=torch.float32, device=dev)
+        pcd = fvsynth.pca(D, 0)
+        hpd = fv.pca_load(pcd.A, pcd.mean)
+        dsift = {"config": {"H": Hi, "W": Wi, "scales": 8, "bin": 4, "step": 4,
+                            "rows_per_image": rows_per, "K": K, "D": D}, "runs": {}}
+        for name, n in (("frame", 1), ("batch", nimg)):
+            im, ro = imgs[:n], rows_out[:n]
+
+            def dstep(im=im, ro=ro):
+                fv.dsift(im, out=ro, flags=fv.ASYNC, stream=stream)
+            steps = 200 if n == 1 else 20
+            _, per, _ = time_steps(torch, dstep, steps, 5, stream)
+            ms = float(np.median(per))
+            gbytes = n * (4.0 * Hi * Wi + 4.0 * fv.DSIFT_DIM * rows_per)
+            run = {"images": n, "dsift_ms": ms, "dsift_ms_per_image": ms / n,
+                   "dsift_rows_per_s": n * rows_per / (ms * 1e-3),
+                   "dsift_gbps": round(gbytes / (ms * 1e-3) / 1e9, 1), "encode_images": {}}
+            for form in forms:
+                outi = torch.empty(n, 2 * K * D, dtype=torch.float32, device=dev)
+
+                def estep(im=im, outi=outi, prec=PREC_CODE[form]):
+                    fv.encode_images(h, hpd, im, out=outi, precision=prec, flags=fv.ASYNC,
+                                     stream=stream)
+                _, per, _ = time_steps(torch, estep, steps, 5, stream)
+                ems = float(np.median(per))
+                run["encode_images"][form] = {"ms": ems, "ms_per_image": ems / n,
+                                              "images_per_s": n / (ems * 1e-3)}
+            dsift["runs"][name] = run
+            log(f"[bench] dense SIFT {name} ({n} x {Wi}x{Hi}): {ms / n:.4f} ms/image, "
+                f"{run['dsift_gbps']} GB/s; image->FV " +
+                ", ".join(f"{f} {v['ms_per_image']:.4f} ms/image"
+                          for f, v in run["encode_images"].items()))
+        hpd.free()
+
     # EM training step on the batch's descriptors as one training set (the encoder's first
     # pass and statistics pass, then the M-step and log-likelihood reductions)
     em = {}
@@ -778,6 +823,13 @@ def main():
             "forms": em,
             "note": "one EM iteration (host-returned model and log-likelihood) over all rows of "
                     "the 64-frame batch as one training set, K = 256, D = 64"}
+    if dsift:
+        dsift["note"] = ("synthetic frames (fvsynth.images); dsift_gbps = (image bytes + 520 "
+                         "bytes per descriptor row) / median time; encode_images = dense SIFT, "
+                         "projection 130 -> 64 and the batched encode of each image's rows, one "
+                         "vector per image (the paper: 34 ms per 320x240 frame for dense SIFT + "
+                         "FV at K = 256, D = 82 on a K40)")
+        result["dense_sift"] = dsift
     if projected:
         result["projected_din130"] = {
             "forms": projected,

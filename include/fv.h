@@ -334,6 +334,8 @@ typedef struct fv_server_stats {
   double p50_ms, p99_ms, max_ms;  /* submit-to-done latency of completed requests */
   double busy_s;                  /* wall time with at least one launch in flight */
   int64_t cancelled;              /* requests withdrawn by fv_server_cancel */
+  int64_t graph_captures;         /* graphs captured on the server's streams (not reset) */
+  int64_t graph_replays;          /* graph replays on the server's streams (not reset) */
 } fv_server_stats;
 
 /* Fill a config with the defaults above (budget unlimited, FP32, HIP executor). */
@@ -379,6 +381,12 @@ int fv_server_next_done(fv_server* srv, double timeout_ms, uint64_t* ticket);
 
 /* Aggregate counters and latency percentiles since creation (or the last reset). */
 int fv_server_get_stats(fv_server* srv, fv_server_stats* st, int reset);
+
+/* Graph captures and replays of libfv's launch sequences since the process started, over all
+ * devices and streams (monitoring: a capture instantiates a new executable graph, which costs
+ * far more than a replay).  Batches on one stream share a graph while they fit its capacities
+ * (frames, chunks, rows; doubled when exceeded); single frames are keyed by their size. */
+int fv_graph_counters(int64_t* captures, int64_t* replays);
 
 /* Static description of a status code. */
 const char* fv_strerror(int code);

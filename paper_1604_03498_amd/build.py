@@ -23,6 +23,13 @@ SOURCES = ["fv_api.cpp", "fv_server.cpp", "fv_kernels.hip", "fv_split.hip", "fv_
            "fv_dsift.hip", "fv_dsift_host.cpp",
            "fv_form_bf16s.hip", "fv_form_f16s.hip", "fv_form_bf16.hip", "fv_project.hip",
            "fv_em.hip"]
+# Statistics kernels built without NaN-preserving max semantics: every fmaxf of an MFMA or
+# lane-exchange result otherwise gets a canonicalising v_max per input (about 60 extra VALU per
+# 32-row wave-tile in the row maxima).  A NaN descriptor still makes its frame's statistics
+# NaN (it reaches every sum through exp2); the finalize, whose signed square root maps NaN to 0
+# by comparisons, keeps IEEE semantics.
+NO_NAN_SOURCES = {"fv_kernels.hip", "fv_split.hip", "fv_form_bf16s.hip", "fv_form_f16s.hip",
+                  "fv_form_bf16.hip"}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -34,10 +41,11 @@ def hipcc_flags():
             "-I", INCLUDE, "-I", CSRC]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB) -> str:
     with tempfile.TemporaryDirectory(prefix="fvbuild_") as td:
         objs = [os.path.join(td, src + ".o") for src in SOURCES]
-        cmds = [[HIPCC] + hipcc_flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds = [[HIPCC] + hipcc_flags() + (["-fno-honor-nans"] if src in NO_NAN_SOURCES else []) +
+                ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
                 for src, obj in zip(SOURCES, objs)]
         procs = []
         for cmd in cmds:
@@ -57,10 +65,13 @@ def build(verbose: bool = False) -> str:
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("link failed:\n" + r.stderr)
-        shutil.copyfile(tmp_lib, LIB + ".tmp")
-        os.replace(LIB + ".tmp", LIB)
-    return LIB
+        shutil.copyfile(tmp_lib, out + ".tmp")
+        os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    # python -m paper_1604_03498_amd.build [-v] [--out PATH]  (default: in-tree libfv.so)
+    args = sys.argv[1:]
+    dest = args[args.index("--out") + 1] if "--out" in args else LIB
+    print(build(verbose="-v" in args, out=dest))

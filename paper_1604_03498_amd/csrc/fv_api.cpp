@@ -115,6 +115,17 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
 };
 
+// A capacity that holds `need`: unchanged if it does, else at least doubled (and >= lo).
+int grow_cap(int cur, int need, int lo) {
+  if (need <= cur) return cur;
+  int64_t c = std::max<int64_t>({(int64_t)need, 2 * (int64_t)cur, (int64_t)lo});
+  return (int)std::min<int64_t>(c, (int64_t)1 << 30);
+}
+int64_t grow_cap64(int64_t cur, int64_t need, int64_t lo) {
+  if (need <= cur) return cur;
+  return std::max<int64_t>({need, 2 * cur, lo});
+}
+
 struct Workspace {
   std::mutex mu;
   char* dev = nullptr;
@@ -124,7 +135,11 @@ struct Workspace {
   hipEvent_t pin_done = nullptr;  // last H2D copy out of `pinned`
   bool pin_pending = false;
   std::vector<GraphEntry> graphs;  // most recent last
+  fv::BatchCaps caps;  // of the batched sequence (grow by doubling, or set by batch_reserve)
+  int64_t captures = 0, replays = 0;  // graph captures and replays on this stream
 };
+
+std::atomic<int64_t> g_graph_captures{0}, g_graph_replays{0};
 
 constexpr size_t kMaxGraphs = 8;
 
@@ -151,6 +166,8 @@ int run_sequence(Workspace* ws, const GraphKey& key, bool use_graph, hipStream_t
       ws->graphs.erase(ws->graphs.begin() + (long)i);
       ws->graphs.push_back(e);
       FV_HIP(hipGraphLaunch(e.exec, s));
+      ++ws->replays;
+      g_graph_replays.fetch_add(1, std::memory_order_relaxed);
       return FV_OK;
     }
   FV_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -171,6 +188,8 @@ int run_sequence(Workspace* ws, const GraphKey& key, bool use_graph, hipStream_t
     ws->graphs.erase(ws->graphs.begin());
   }
   ws->graphs.push_back(GraphEntry{key, ex});
+  ++ws->captures;
+  g_graph_captures.fetch_add(1, std::memory_order_relaxed);
   FV_HIP(hipGraphLaunch(ex, s));
   return FV_OK;
 }
@@ -488,28 +507,100 @@ int project_grid(int device, int64_t N) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)device_cu_count(device) * 2));
 }
 
+// Byte layout of a stream's batch workspace for capacities `cp`: partial slots, finalize
+// norm parts, first-pass normalisers (two-pass path), the work table (Counts record, frames,
+// items, groups), staging of host X and host out, and the projected rows.
+struct BatchLayout {
+  size_t part = 0, norm = 0, lse = 0, cnt = 0, frames = 0, items = 0, groups = 0;
+  size_t x = 0, out = 0, y = 0;
+  size_t tab() const { return cnt + frames + items + groups; }
+  size_t total() const { return part + norm + lse + tab() + x + out + y; }
+};
+
+BatchLayout batch_layout(const fv::Consts& c, Path path, const fv::BatchCaps& cp, int Din,
+                         unsigned flags, bool pca) {
+  BatchLayout l;
+  const size_t out_len = (size_t)2 * c.K * c.D;
+  l.part = align256((size_t)cp.items * fv::slot_floats(c) * 4);
+  l.norm = align256((size_t)cp.B * fv::finalize_blocks(c) * 8);
+  l.lse = (path == Path::kSplit) ? align256((size_t)fv::lse_groups(c) * cp.rows * 8) : 0;
+  l.cnt = align256(sizeof(fv::Counts));
+  l.frames = align256((size_t)cp.B * sizeof(fv::Frame));
+  l.items = align256((size_t)cp.items * sizeof(fv::Item));
+  l.groups = align256((size_t)cp.groups * sizeof(fv::Group));
+  l.x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)cp.rows * Din * 4);
+  l.out = (flags & FV_OUT_DEVICE) ? 0 : align256((size_t)cp.B * out_len * 4);
+  l.y = pca ? align256((size_t)cp.rows * c.D * 4) : 0;
+  return l;
+}
+
 }  // namespace
 
 namespace fv {
-size_t batch_device_bytes(const fv_gmm* g, const int64_t* sizes, int B, int precision) {
-  const Consts& c = g->c;
-  const bool split = choose_batch(g, precision) == Path::kSplit;
+void stream_graph_counts(int device, hipStream_t s, int64_t* captures, int64_t* replays) {
+  Workspace* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({device, s});
+    if (it != g_ws.end()) ws = it->second.get();
+  }
+  int64_t c = 0, r = 0;
+  if (ws) {
+    std::lock_guard<std::mutex> lk(ws->mu);
+    c = ws->captures;
+    r = ws->replays;
+  }
+  if (captures) *captures = c;
+  if (replays) *replays = r;
+}
+
+BatchCaps batch_need(const fv_gmm* g, const int64_t* sizes, int B) {
   const int P = batch_chunk(g);
-  int64_t rows = 0, items = 0, groups = 0;
+  BatchCaps n;
+  n.B = B;
+  int64_t items = 0, groups = 0;
   for (int b = 0; b < B; ++b) {
     const int64_t ni = (sizes[b] + P - 1) / P;
-    rows += sizes[b];
+    n.rows += sizes[b];
     items += ni;
     groups += (ni + kGroupItems - 1) / kGroupItems;
   }
-  const size_t out_len = (size_t)2 * c.K * c.D;
-  size_t n = align256((size_t)items * slot_floats(c) * 4) +
-             align256((size_t)B * finalize_blocks(c) * 8) +
-             (split ? align256((size_t)lse_groups(c) * rows * 8) : 0) +
-             align256((size_t)B * sizeof(Frame)) + align256((size_t)items * sizeof(Item)) +
-             align256((size_t)groups * sizeof(Group));
-  n += align256((size_t)rows * c.D * 4) + align256((size_t)B * out_len * 4);
+  n.items = (int)std::min<int64_t>(items, (int64_t)1 << 30);
+  n.groups = (int)std::min<int64_t>(groups, (int64_t)1 << 30);
   return n;
+}
+
+size_t batch_caps_bytes(const fv_gmm* g, int precision, const BatchCaps& caps) {
+  return batch_layout(g->c, choose_batch(g, precision), caps, g->D, FV_X_DEVICE | FV_OUT_DEVICE,
+                      false)
+      .total();
+}
+
+int batch_reserve(const fv_gmm* g, int precision, hipStream_t s, const BatchCaps& caps,
+                  size_t* bytes) {
+  if (!g || !bytes) return FV_E_INVAL;
+  DeviceGuard dg(g->device);
+  if (dg.status() != hipSuccess) return hip_fail(dg.status());
+  Workspace* ws = workspace_for(g->device, s);
+  if (!ws) return FV_E_NOMEM;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  const size_t need = batch_caps_bytes(g, precision, caps);
+  if (need != ws->dev_cap) {
+    if (ws->dev) {
+      FV_HIP(hipStreamSynchronize(s));
+      drop_graphs(ws);
+      FV_HIP(hipFree(ws->dev));
+      ws->dev = nullptr;
+      ws->dev_cap = 0;
+    }
+    if (need > 0) {
+      FV_HIP(hipMalloc(&ws->dev, need));
+      ws->dev_cap = need;
+    }
+  }
+  ws->caps = caps;
+  *bytes = ws->dev_cap;
+  return FV_OK;
 }
 }  // namespace fv
 
@@ -573,6 +664,12 @@ const char* fv_strerror(int code) {
 }
 
 int fv_last_device_error(void) { return t_last_hip_error; }
+
+int fv_graph_counters(int64_t* captures, int64_t* replays) {
+  if (captures) *captures = g_graph_captures.load(std::memory_order_relaxed);
+  if (replays) *replays = g_graph_replays.load(std::memory_order_relaxed);
+  return FV_OK;
+}
 
 int fv_stream_release(int device, void* hip_stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1030,19 +1127,20 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   if (!ws) return FV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ws->mu);
 
-  const int G = fv::lse_groups(c);
-  const int nblk = fv::finalize_blocks(c);
+  // The launch sequence is sized to the workspace's capacities (frames, items, chunk groups,
+  // rows), which only grow (doubling), and the kernels read the batch's own sizes from the
+  // Counts record at the head of the work table: one captured graph serves every batch that
+  // fits the capacities, whatever its frame sizes.
+  fv::BatchCaps& cp = ws->caps;
+  cp.B = std::max(cp.B, grow_cap(cp.B, B, 8));
+  cp.items = std::max(cp.items, grow_cap(cp.items, n_items, 64));
+  cp.groups = std::max(cp.groups, grow_cap(cp.groups, n_groups, 8));
+  cp.rows = std::max(cp.rows, grow_cap64(cp.rows, rows, (int64_t)1 << 16));
   const size_t out_len = (size_t)2 * c.K * c.D;
-  const size_t b_part = align256((size_t)n_items * fv::slot_floats(c) * 4);
-  const size_t b_norm = align256((size_t)B * nblk * 8);
-  const size_t b_lse = (path == Path::kSplit) ? align256((size_t)G * rows * 8) : 0;
-  const size_t b_frames = align256((size_t)B * sizeof(fv::Frame));
-  const size_t b_items = align256((size_t)n_items * sizeof(fv::Item));
-  const size_t b_groups = align256((size_t)n_groups * sizeof(fv::Group));
-  const size_t b_tab = b_frames + b_items + b_groups;
-  const size_t b_x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)rows * Din * 4);
-  const size_t b_out = (flags & FV_OUT_DEVICE) ? 0 : align256((size_t)B * out_len * 4);
-  const size_t b_y = pca ? align256((size_t)rows * c.D * 4) : 0;
+  const BatchLayout lay = batch_layout(c, path, cp, Din, flags, pca != nullptr);
+  const size_t b_part = lay.part, b_norm = lay.norm, b_lse = lay.lse, b_cnt = lay.cnt;
+  const size_t b_frames = lay.frames, b_items = lay.items, b_tab = lay.tab();
+  const size_t b_x = lay.x, b_out = lay.out, b_y = lay.y;
   int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_tab + b_x + b_out + b_y, s);
   if (rc) return rc;
   rc = ensure_pinned(ws, b_tab);
@@ -1052,17 +1150,22 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   double* normpart = reinterpret_cast<double*>(base + b_part);
   float2* lse = reinterpret_cast<float2*>(base + b_part + b_norm);
   char* tab = base + b_part + b_norm + b_lse;
-  fv::Frame* dframes = reinterpret_cast<fv::Frame*>(tab);
-  fv::Item* ditems = reinterpret_cast<fv::Item*>(tab + b_frames);
-  fv::Group* dgroups = reinterpret_cast<fv::Group*>(tab + b_frames + b_items);
+  const fv::Counts* dcounts = reinterpret_cast<const fv::Counts*>(tab);
+  fv::Frame* dframes = reinterpret_cast<fv::Frame*>(tab + b_cnt);
+  fv::Item* ditems = reinterpret_cast<fv::Item*>(tab + b_cnt + b_frames);
+  fv::Group* dgroups = reinterpret_cast<fv::Group*>(tab + b_cnt + b_frames + b_items);
   float* xdev = reinterpret_cast<float*>(tab + b_tab);
   float* odev = reinterpret_cast<float*>(tab + b_tab + b_x);
   float* ydev = reinterpret_cast<float*>(tab + b_tab + b_x + b_out);
 
-  // work tables in pinned memory (same layout as on the device), then one H2D copy
-  fv::Frame* hframes = reinterpret_cast<fv::Frame*>(ws->pinned);
-  fv::Item* hitems = reinterpret_cast<fv::Item*>(ws->pinned + b_frames);
-  fv::Group* hgroups = reinterpret_cast<fv::Group*>(ws->pinned + b_frames + b_items);
+  // work tables in pinned memory (same layout as on the device), then one H2D copy of the
+  // whole capacity
+  char* pin = ws->pinned;
+  fv::Counts* hcounts = reinterpret_cast<fv::Counts*>(pin);
+  fv::Frame* hframes = reinterpret_cast<fv::Frame*>(pin + b_cnt);
+  fv::Item* hitems = reinterpret_cast<fv::Item*>(pin + b_cnt + b_frames);
+  fv::Group* hgroups = reinterpret_cast<fv::Group*>(pin + b_cnt + b_frames + b_items);
+  *hcounts = fv::Counts{rows, n_items, (int32_t)((rows + fv::kTile - 1) / fv::kTile), B, 0};
   std::memcpy(hframes, frames.data(), (size_t)B * sizeof(fv::Frame));
   {
     int64_t i = 0, gi = 0;
@@ -1088,38 +1191,44 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   float* Od = (flags & FV_OUT_DEVICE) ? out : odev;
   const float* Fx = pca ? ydev : Xd;  // the encoder's input
   const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Fx) & 15) == 0);
-  // One persistent statistics launch over the work table (grid = resident workgroups), then
-  // the finalize; the table copy from pinned memory is part of the sequence.
+  fv::Consts cc = c;
+  cc.cnt = dcounts;
+  // The table copy, the projection (if any), one persistent statistics launch over the items
+  // (grid = resident workgroups) or the two passes, then the finalize over the frame capacity
+  // (slots past the batch exit at once).  Every grid depends on the capacities only.
   auto enqueue = [&]() -> int {
-    FV_HIP(hipMemcpyAsync(dframes, ws->pinned, b_tab, hipMemcpyHostToDevice, s));
-    if (pca && rows > 0) {
+    FV_HIP(hipMemcpyAsync(tab, ws->pinned, b_tab, hipMemcpyHostToDevice, s));
+    if (pca) {
       hipEvent_t tp = timing_begin(s);
-      FV_HIP(fv::launch_project(pca->p, Xd, rows, ydev, project_grid(gmm->device, rows), s));
+      FV_HIP(fv::launch_project(pca->p, Xd, cp.rows, ydev, project_grid(gmm->device, cp.rows),
+                                s, dcounts));
       timing_end(tp, 2, s);
     }
-    if (n_items > 0) {
-      hipEvent_t t0 = timing_begin(s);
-      if (path == Path::kFused) {
-        const int grid = grid_cap(std::max(1, std::min(n_items, resident_fused(gmm->device, c.Wg))));
-        FV_HIP(run_stats(c, precision, Fx, vec_ok, rows, P, ditems, n_items, grid, partials, s));
-      } else {
-        const int n_tiles = (int)((rows + fv::kTile - 1) / fv::kTile);
-        const int grid1 = grid_cap(std::min(n_tiles, resident_fused(gmm->device, c.Wg)));
-        FV_HIP(run_lse(c, precision, Fx, vec_ok, rows, n_tiles, grid1, lse, rows, s));
-        const int groups = normext_groups(c);
-        const int grid2 = grid_cap(xcd_grid(std::max(1, std::min(n_items, (device_cu_count(gmm->device) + groups - 1) / groups))));
-        FV_HIP(run_normext(c, precision, Fx, vec_ok, rows, P, ditems, n_items, grid2, lse, rows, partials, s));
-      }
-      timing_end(t0, 0, s);
+    hipEvent_t t0 = timing_begin(s);
+    const int resident = resident_fused(gmm->device, c.Wg);
+    if (path == Path::kFused) {
+      FV_HIP(run_stats(cc, precision, Fx, vec_ok, cp.rows, P, ditems, cp.items,
+                       grid_cap(resident), partials, s));
+    } else {
+      const int tiles_cap = (int)((cp.rows + fv::kTile - 1) / fv::kTile);
+      FV_HIP(run_lse(cc, precision, Fx, vec_ok, cp.rows, tiles_cap, grid_cap(resident), lse,
+                     cp.rows, s));
+      const int groups = normext_groups(c);
+      const int grid2 = grid_cap(xcd_grid((device_cu_count(gmm->device) + groups - 1) / groups));
+      FV_HIP(run_normext(cc, precision, Fx, vec_ok, cp.rows, P, ditems, cp.items, grid2, lse,
+                         cp.rows, partials, s));
     }
+    timing_end(t0, 0, s);
     hipEvent_t t1 = timing_begin(s);
-    FV_HIP(fv::launch_finalize(c, partials, dframes, fv::Frame{0, 0, 0, 0, 0}, B, dgroups, flags, Od,
-                               normpart, s));
+    FV_HIP(fv::launch_finalize(cc, partials, dframes, fv::Frame{0, 0, 0, 0, 0}, cp.B, dgroups,
+                               flags, Od, normpart, s));
     timing_end(t1, 1, s);
     return FV_OK;
   };
+  // (a batch without rows runs directly: its X may be any pointer, even null, and there is
+  // nothing to replay)
   const bool use_graph = graphs_enabled() && s != nullptr && (flags & FV_X_DEVICE) &&
-                         (flags & FV_OUT_DEVICE) && !timing_enabled();
+                         (flags & FV_OUT_DEVICE) && !timing_enabled() && rows > 0;
   GraphKey key;
   key.kind = 1;
   key.gmm = gmm->serial;
@@ -1127,10 +1236,10 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   key.flags = flags & kGraphFlags;
   key.path = (int)path;
   key.P = P;
-  key.rows = rows;
-  key.B = B;
-  key.n_items = n_items;
-  key.n_groups = n_groups;
+  key.rows = cp.rows;
+  key.B = cp.B;
+  key.n_items = cp.items;
+  key.n_groups = cp.groups;
   key.X = Xd;
   key.out = Od;
   key.dev = ws->dev;
@@ -1155,14 +1264,16 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
 }  // extern "C"
 
 namespace fv {
-int encode_with_scratch(const fv_gmm* gmm, const float* X, int64_t N, float* out, int precision,
-                        unsigned flags, void* hip_stream, char* scratch, size_t scratch_bytes) {
+int encode_on_scratch(const fv_gmm* gmm, const float* X, int64_t N, float* out, int precision,
+                      unsigned flags, void* hip_stream, char* scratch, size_t scratch_bytes) {
   if (!gmm || !scratch) return FV_E_INVAL;
   if ((flags & (FV_X_DEVICE | FV_OUT_DEVICE)) != (FV_X_DEVICE | FV_OUT_DEVICE)) return FV_E_INVAL;
   return encode_impl(gmm, nullptr, X, N, out, precision, flags, hip_stream, scratch,
                      scratch_bytes);
 }
+}  // namespace fv
 
+namespace fv {
 int set_device(int device) {
   const hipError_t e = hipSetDevice(device);
   return e == hipSuccess ? FV_OK : hip_fail(e);

@@ -51,9 +51,10 @@ __global__ __launch_bounds__(kRedThreads) void reduce_assemble_kernel(
     const double* __restrict__ mu64, const double* __restrict__ isd64,
     const double* __restrict__ ivar64, const double* __restrict__ cu64,
     const double* __restrict__ cv64, unsigned flags, float* __restrict__ out,
-    double* __restrict__ normpart) {
+    double* __restrict__ normpart, const Counts* __restrict__ cnt) {
   __shared__ double sv[3][kCompBlock];
   const int b = blockIdx.y;
+  if (cnt && b >= cnt->B) return;  // a frame slot past the batch (grid sized to a capacity)
   const Frame fr = frames != nullptr ? frames[b] : single;
   const int kb = blockIdx.x % nkb;
   const int d = blockIdx.x / nkb;
@@ -137,9 +138,11 @@ __global__ __launch_bounds__(kRedThreads) void reduce_assemble_kernel(
 
 __global__ __launch_bounds__(kThreads) void l2_kernel(float* __restrict__ out,
                                                       const double* __restrict__ normpart,
-                                                      int nblk, int len) {
+                                                      int nblk, int len,
+                                                      const Counts* __restrict__ cnt) {
   __shared__ double red[kThreads];
   const int b = blockIdx.y;
+  if (cnt && b >= cnt->B) return;
   // this thread's output values are loaded first, so their latency overlaps the norm's sum
   float* o = out + (size_t)b * len;
   const int base = blockIdx.x * kThreads * kL2PerThread + threadIdx.x;
@@ -179,14 +182,14 @@ hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* 
   const int nkb = (c.K + kCompBlock - 1) / kCompBlock;
   hipLaunchKernelGGL(reduce_assemble_kernel, dim3(nblk, B), dim3(kRedThreads), 0, stream, partials,
                      frames, single, groups, c.K, c.D, c.DP, c.Kp, nkb, c.mu64, c.isd64, c.ivar64,
-                     c.cu64, c.cv64, flags, out, normpart);
+                     c.cu64, c.cv64, flags, out, normpart, c.cnt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!(flags & kFlagNoL2)) {
     const int len = 2 * c.K * c.D;
     const int per_blk = kThreads * kL2PerThread;
     hipLaunchKernelGGL(l2_kernel, dim3((len + per_blk - 1) / per_blk, B), dim3(kThreads), 0,
-                       stream, out, normpart, nblk, len);
+                       stream, out, normpart, nblk, len, c.cnt);
     e = hipGetLastError();
   }
   return e;

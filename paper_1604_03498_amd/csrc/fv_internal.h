@@ -19,12 +19,30 @@ constexpr int kMaxWaves = 8;      // 8 waves x 32 components = 256 components pe
 constexpr int kFusedMaxK = kCompsPerWave * kMaxWaves;  // fused single-pass kernel
 constexpr int kMaxK = 1024;                               // two-pass path
 constexpr int kMaxD = 96;
-#ifndef FV_NOALLOC_SCRATCH_BYTES
-#define FV_NOALLOC_SCRATCH_BYTES (64u << 20)
-#endif
 // The paper's posterior threshold (Algorithm 1): with it on, a term enters the statistics only
 // if its posterior exceeds kTau.
 constexpr float kTau = 1e-6f;
+
+// Sizes of one batched launch sequence, read by its kernels from device memory at the head of
+// the work table, so that a captured graph serves every batch within its capacities: rows
+// (arithmetic 32-row tiles of the first pass run to it), statistics items, 32-row tiles and
+// frames.  Kernels given a null pointer use their arguments instead.
+struct Counts {
+  int64_t rows;
+  int32_t n_items;
+  int32_t n_tiles;
+  int32_t B;
+  int32_t pad;
+};
+
+// Loop bound of a grid-stride kernel: work items from the table (statistics chunks, or the
+// arithmetic 32-row tiles when there is no item table), else the launch argument.
+__device__ __forceinline__ int live_items(const Counts* cnt, const void* items, int n) {
+  return cnt ? (items ? cnt->n_items : cnt->n_tiles) : n;
+}
+__device__ __forceinline__ int64_t live_rows(const Counts* cnt, int64_t n) {
+  return cnt ? cnt->rows : n;
+}
 
 // Device-resident constants of one GMM (all pointers are device memory owned by the handle).
 struct Consts {
@@ -58,6 +76,8 @@ struct Consts {
   const double* cv64;    // 1/sqrt(2 w)
   // Per call, not per model: nonzero applies kTau (the API sets it on its own copy)
   int thresh;
+  // Per call: the batched sequence's device-side sizes (null: the launch arguments hold them)
+  const Counts* cnt;
 };
 
 // A chunk of consecutive descriptor rows whose statistics go to one partial slot.
@@ -143,17 +163,46 @@ int finalize_blocks(const Consts& c);
 
 // fv_encode with every intermediate in the caller's device scratch (scratch_bytes at scratch):
 // X and out in device memory (both FV_X_DEVICE and FV_OUT_DEVICE set), no allocation, no
-// graph, no timing events; FV_E_UNSUPPORTED when the frame's intermediates do not fit.
-int encode_with_scratch(const struct ::fv_gmm* gmm, const float* X, int64_t N, float* out,
-                        int precision, unsigned flags, void* hip_stream, char* scratch,
-                        size_t scratch_bytes);
+// graph, no timing events; FV_E_UNSUPPORTED (before any launch) when the frame's
+// intermediates do not fit.
+int encode_on_scratch(const struct ::fv_gmm* gmm, const float* X, int64_t N, float* out,
+                      int precision, unsigned flags, void* hip_stream, char* scratch,
+                      size_t scratch_bytes);
 // hipSetDevice, and a HIP error turned into an FV_E_* code (recorded for fv_last_device_error).
 int set_device(int device);
 int device_error(hipError_t e);
 
-// Device bytes one fv_encode_batch call needs for frames of the given sizes (workspace plus
-// device-resident X and out), used by the server's admission control.
-size_t batch_device_bytes(const struct ::fv_gmm* g, const int64_t* sizes, int B, int precision);
+// Graph captures and replays so far of the launch sequences on (device, stream) (zero for a
+// pair never used).
+void stream_graph_counts(int device, hipStream_t s, int64_t* captures, int64_t* replays);
+
+// Capacities a stream's batched launch sequence is sized to: frames, statistics chunks, chunk
+// groups and rows.  Its grids and buffers depend on these only.
+struct BatchCaps {
+  int B = 0, items = 0, groups = 0;
+  int64_t rows = 0;
+  bool operator==(const BatchCaps& o) const {
+    return B == o.B && items == o.items && groups == o.groups && rows == o.rows;
+  }
+};
+inline BatchCaps caps_max(const BatchCaps& a, const BatchCaps& b) {
+  BatchCaps m;
+  m.B = a.B > b.B ? a.B : b.B;
+  m.items = a.items > b.items ? a.items : b.items;
+  m.groups = a.groups > b.groups ? a.groups : b.groups;
+  m.rows = a.rows > b.rows ? a.rows : b.rows;
+  return m;
+}
+// The capacities a batch of frames of these sizes needs (the handle's chunk length).
+BatchCaps batch_need(const struct ::fv_gmm* g, const int64_t* sizes, int B);
+// Device bytes of a stream's batch workspace with these capacities on the handle's batched
+// path for `precision` (X and out in device memory, no projection).
+size_t batch_caps_bytes(const struct ::fv_gmm* g, int precision, const BatchCaps& caps);
+// Sets (device, stream)'s batch workspace to exactly these capacities and allocates exactly
+// what they take (growing or shrinking it); later batches within them allocate nothing.
+// *bytes receives the workspace's device bytes.
+int batch_reserve(const struct ::fv_gmm* g, int precision, hipStream_t s, const BatchCaps& caps,
+                  size_t* bytes);
 
 // ---- 16-bit operand forms (one translation unit per form) --------------------------------
 struct Frags16 {
@@ -192,8 +241,10 @@ struct ProjConsts {
   const float* frag;  // [2S][Dp], frag[k][c] = A[c][k] (zero for k >= Din or c >= D)
   const float* bias;  // [Dp], -(A m)[c] computed in double (zero for c >= D)
 };
+// With cnt (a batched sequence) the row count is read from cnt->rows; N is then only the
+// capacity the grid was sized for.
 hipError_t launch_project(const ProjConsts& p, const float* X, int64_t N, float* Y, int grid,
-                          hipStream_t stream);
+                          hipStream_t stream, const Counts* cnt = nullptr);
 
 // EM step (fv_em.hip): M-step from the statistics partials, log-likelihood from the first
 // pass's row normalisers (ll_part: em_loglik_blocks(N) workgroup sums, log2 units).

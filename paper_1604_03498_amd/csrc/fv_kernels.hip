@@ -39,7 +39,7 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
     const Item* __restrict__ items, int n_items, const float* __restrict__ A32,
     const float* __restrict__ c32, const float* __restrict__ cen, int Kp,
     float* __restrict__ partials, float2* __restrict__ lse, int64_t lse_stride,
-    float* __restrict__ gout, int64_t gstride) {
+    float* __restrict__ gout, int64_t gstride, const Counts* __restrict__ cnt) {
   constexpr int NT = 64 * W;
   constexpr int NB = 2 * DP / 32;  // 32-feature output blocks of the statistics contraction
   // At 8 waves (two per SIMD, 256 registers each) the statistics kernel cannot also hold its
@@ -73,7 +73,9 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
   stage_centre<DP, NT>(cs, cen, tid);
 
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  const int n_it = live_items(cnt, items, n_items);
+  const int64_t n_rows = live_rows(cnt, N);
+  for (int it = blockIdx.x; it < n_it; it += gridDim.x) {
     int64_t row0;
     int nrows;
     if (items != nullptr) {
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
       nrows = t.nrows;
     } else {
       row0 = (int64_t)it * P;
-      const int64_t rem = N - row0;
+      const int64_t rem = n_rows - row0;
       nrows = (int)(rem < (int64_t)P ? rem : (int64_t)P);
     }
     const int ntiles = (nrows + kTile - 1) / kTile;
@@ -198,7 +200,8 @@ __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
     const float* __restrict__ X, int D, int vec_ok, int64_t N, int P,
     const Item* __restrict__ items, int n_items, const float2* __restrict__ lse, int G,
     int64_t lse_stride, const float* __restrict__ A32, const float* __restrict__ c32,
-    const float* __restrict__ cen, int Kp, float* __restrict__ partials) {
+    const float* __restrict__ cen, int Kp, float* __restrict__ partials,
+    const Counts* __restrict__ cnt) {
   constexpr int NT = 64 * W;
   constexpr int NB = 2 * DP / 32;
   using IO = TileIO<DP, NT>;
@@ -221,7 +224,9 @@ __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
   stage_centre<DP, NT>(cs, cen, tid);
 
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  const int n_it = live_items(cnt, items, n_items);
+  const int64_t n_rows = live_rows(cnt, N);
+  for (int it = blockIdx.x; it < n_it; it += gridDim.x) {
     int64_t row0;
     int nrows;
     if (items != nullptr) {
@@ -230,7 +235,7 @@ __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
       nrows = t.nrows;
     } else {
       row0 = (int64_t)it * P;
-      const int64_t rem = N - row0;
+      const int64_t rem = n_rows - row0;
       nrows = (int)(rem < (int64_t)P ? rem : (int64_t)P);
     }
     const int ntiles = (nrows + kTile - 1) / kTile;
@@ -321,11 +326,11 @@ hipError_t launch_normext_dp(const Consts& c, const float* X, bool vec_ok, int64
   if (c.thresh)
     hipLaunchKernelGGL((normext_f32_kernel<DP, W, true>), grd, dim3(64 * W), 0, stream, X, c.D,
                        vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c), lse_stride,
-                       c.A32, c.c32, c.cen, c.Kp, partials);
+                       c.A32, c.c32, c.cen, c.Kp, partials, c.cnt);
   else
     hipLaunchKernelGGL((normext_f32_kernel<DP, W, false>), grd, dim3(64 * W), 0, stream, X, c.D,
                        vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c), lse_stride,
-                       c.A32, c.c32, c.cen, c.Kp, partials);
+                       c.A32, c.c32, c.cen, c.Kp, partials, c.cnt);
   return hipGetLastError();
 }
 
@@ -353,7 +358,7 @@ hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N,
     if (c.thresh) {
       hipLaunchKernelGGL((fused_f32_kernel<DP, W, false, true>), dim3(grid, groups), dim3(64 * W),
                          0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32,
-                         c.cen, c.Kp, partials, lse, lse_stride, nullptr, 0);
+                         c.cen, c.Kp, partials, lse, lse_stride, nullptr, 0, c.cnt);
       return hipGetLastError();
     }
   } else {
@@ -363,7 +368,8 @@ hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N,
         if (groups != 1) return hipErrorInvalidValue;
         hipLaunchKernelGGL((fused_f32_kernel<DP, W, true, false, true>), dim3(grid, 1),
                            dim3(64 * W), 0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items,
-                           c.A32, c.c32, c.cen, c.Kp, partials, lse, lse_stride, gout, gstride);
+                           c.A32, c.c32, c.cen, c.Kp, partials, lse, lse_stride, gout, gstride,
+                           c.cnt);
         return hipGetLastError();
       } else {
         return hipErrorInvalidValue;
@@ -372,7 +378,7 @@ hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N,
   }
   hipLaunchKernelGGL((fused_f32_kernel<DP, W, LSE, false>), dim3(grid, groups), dim3(64 * W), 0,
                      stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32, c.cen,
-                     c.Kp, partials, lse, lse_stride, nullptr, 0);
+                     c.Kp, partials, lse, lse_stride, nullptr, 0, c.cnt);
   return hipGetLastError();
 }
 

@@ -34,7 +34,8 @@ __device__ __forceinline__ int prow(int r, int h) { return 8 * (r >> 2) + 4 * h 
 template <int S, int NC, int V>
 __global__ __launch_bounds__(256) void project_kernel(
     const float* __restrict__ X, int64_t N, int Din, const float* __restrict__ frag,
-    const float* __restrict__ bias, int Dp, int D, float* __restrict__ Y) {
+    const float* __restrict__ bias, int Dp, int D, float* __restrict__ Y,
+    const Counts* __restrict__ cnt) {
   constexpr int RB = NC == 3 ? 1 : 4 / NC;
   constexpr int TR = 32 * RB;
   constexpr int kMaxF = TR * 2 * S;
@@ -58,6 +59,7 @@ __global__ __launch_bounds__(256) void project_kernel(
   // clamped in bounds, values past the tile's end replaced by zeros), so that only 8 loads'
   // registers are live; at two workgroups per CU the other workgroup's MFMAs cover the loads.
   using VT = typename VecT<V>::type;
+  N = live_rows(cnt, N);  // a batched sequence's row count (device side), else the argument
   const int64_t ntiles = (N + TR - 1) / TR;
   auto rows_of = [&](int64_t t) { return N - t * TR < TR ? (int)(N - t * TR) : TR; };
   auto copy_tile = [&](int64_t t) {
@@ -117,26 +119,26 @@ __global__ __launch_bounds__(256) void project_kernel(
 
 template <int S, int NC>
 hipError_t launch_snc(const ProjConsts& p, const float* X, int64_t N, int vec, float* Y,
-                      int grid, hipStream_t stream) {
+                      int grid, hipStream_t stream, const Counts* cnt) {
   if (vec == 4)
     hipLaunchKernelGGL((project_kernel<S, NC, 4>), dim3(grid), dim3(256), 0, stream, X, N, p.Din,
-                       p.frag, p.bias, p.Dp, p.D, Y);
+                       p.frag, p.bias, p.Dp, p.D, Y, cnt);
   else if (vec == 2)
     hipLaunchKernelGGL((project_kernel<S, NC, 2>), dim3(grid), dim3(256), 0, stream, X, N, p.Din,
-                       p.frag, p.bias, p.Dp, p.D, Y);
+                       p.frag, p.bias, p.Dp, p.D, Y, cnt);
   else
     hipLaunchKernelGGL((project_kernel<S, NC, 1>), dim3(grid), dim3(256), 0, stream, X, N, p.Din,
-                       p.frag, p.bias, p.Dp, p.D, Y);
+                       p.frag, p.bias, p.Dp, p.D, Y, cnt);
   return hipGetLastError();
 }
 
 template <int S>
 hipError_t launch_s(const ProjConsts& p, const float* X, int64_t N, int vec, float* Y,
-                    int grid, hipStream_t stream) {
+                    int grid, hipStream_t stream, const Counts* cnt) {
   switch (p.Dp / 32) {
-    case 1: return launch_snc<S, 1>(p, X, N, vec, Y, grid, stream);
-    case 2: return launch_snc<S, 2>(p, X, N, vec, Y, grid, stream);
-    case 3: return launch_snc<S, 3>(p, X, N, vec, Y, grid, stream);
+    case 1: return launch_snc<S, 1>(p, X, N, vec, Y, grid, stream, cnt);
+    case 2: return launch_snc<S, 2>(p, X, N, vec, Y, grid, stream, cnt);
+    case 3: return launch_snc<S, 3>(p, X, N, vec, Y, grid, stream, cnt);
     default: return hipErrorInvalidValue;
   }
 }
@@ -144,20 +146,20 @@ hipError_t launch_s(const ProjConsts& p, const float* X, int64_t N, int vec, flo
 }  // namespace
 
 hipError_t launch_project(const ProjConsts& p, const float* X, int64_t N, float* Y, int grid,
-                          hipStream_t stream) {
+                          hipStream_t stream, const Counts* cnt) {
   if (N <= 0) return hipSuccess;
   // widest load the row layout and X's alignment allow (tiles start at multiples of Din)
   const uintptr_t a = reinterpret_cast<uintptr_t>(X);
   const int vec = (a % 16 == 0 && p.Din % 4 == 0) ? 4 : (a % 8 == 0 && p.Din % 2 == 0) ? 2 : 1;
   switch (p.S / 16) {
-    case 1: return launch_s<16>(p, X, N, vec, Y, grid, stream);
-    case 2: return launch_s<32>(p, X, N, vec, Y, grid, stream);
-    case 3: return launch_s<48>(p, X, N, vec, Y, grid, stream);
-    case 4: return launch_s<64>(p, X, N, vec, Y, grid, stream);
-    case 5: return launch_s<80>(p, X, N, vec, Y, grid, stream);
-    case 6: return launch_s<96>(p, X, N, vec, Y, grid, stream);
-    case 7: return launch_s<112>(p, X, N, vec, Y, grid, stream);
-    case 8: return launch_s<128>(p, X, N, vec, Y, grid, stream);
+    case 1: return launch_s<16>(p, X, N, vec, Y, grid, stream, cnt);
+    case 2: return launch_s<32>(p, X, N, vec, Y, grid, stream, cnt);
+    case 3: return launch_s<48>(p, X, N, vec, Y, grid, stream, cnt);
+    case 4: return launch_s<64>(p, X, N, vec, Y, grid, stream, cnt);
+    case 5: return launch_s<80>(p, X, N, vec, Y, grid, stream, cnt);
+    case 6: return launch_s<96>(p, X, N, vec, Y, grid, stream, cnt);
+    case 7: return launch_s<112>(p, X, N, vec, Y, grid, stream, cnt);
+    case 8: return launch_s<128>(p, X, N, vec, Y, grid, stream, cnt);
     default: return hipErrorInvalidValue;
   }
 }

@@ -103,9 +103,16 @@ struct Lane {  // one stream and its device buffers
   size_t dX_cap = 0;  // floats
   float* dOut = nullptr;
   size_t dOut_cap = 0;
+  fv::BatchCaps caps;  // of the encoder workspace on this lane's stream
+  size_t ws_bytes = 0; // device bytes of that workspace
+  // Device bytes this lane holds against the budget: its buffers and encoder workspace (HIP
+  // executor; kept between launches), or the estimate of the batch in flight (fake executor).
+  size_t held = 0;
   bool busy = false;
   std::vector<Request*> batch;
-  size_t bytes = 0;
+  // what the admitted batch needs (HIP executor): buffer sizes and workspace capacities
+  size_t need_x = 0, need_o = 0;
+  fv::BatchCaps need_caps;
   double fake_done_at = 0;
   int fake_status = FV_OK;
 };
@@ -145,13 +152,59 @@ struct fv_server {
 
 namespace {
 
-size_t footprint(const fv_server* s, const std::vector<int64_t>& sizes) {
+// What lane L would hold after taking a batch of frames of these sizes: its buffers and its
+// encoder workspace grown (never shrunk) to fit the batch (HIP executor), or the batch's
+// device footprint estimate (fake executor, which holds nothing between batches).
+struct Need {
+  size_t bytes = 0, x = 0, o = 0;  // x, o in floats
+  fv::BatchCaps caps;
+};
+
+Need lane_need(const fv_server* s, const Lane& L, const std::vector<int64_t>& sizes) {
+  Need n;
+  int64_t rows = 0;
+  for (int64_t r : sizes) rows += r;
   if (s->cfg.executor == FV_EXEC_FAKE || !s->gmm) {
-    size_t n = 0;
-    for (int64_t r : sizes) n += (size_t)r * s->D * 4 + s->out_len * 4;
+    for (int64_t r : sizes) n.bytes += (size_t)r * s->D * 4 + s->out_len * 4;
     return n;
   }
-  return fv::batch_device_bytes(s->gmm, sizes.data(), (int)sizes.size(), s->cfg.precision);
+  n.x = std::max(L.dX_cap, (size_t)rows * s->D);
+  n.o = std::max(L.dOut_cap, sizes.size() * s->out_len);
+  n.caps = fv::caps_max(L.caps, fv::batch_need(s->gmm, sizes.data(), (int)sizes.size()));
+  n.bytes = (n.x + n.o) * 4 + fv::batch_caps_bytes(s->gmm, s->cfg.precision, n.caps);
+  return n;
+}
+
+size_t held_by_others(const fv_server* s, const Lane& L) {
+  size_t n = 0;
+  for (const Lane& M : s->lanes)
+    if (&M != &L) n += M.held;
+  return n;
+}
+
+void update_admitted(fv_server* s) {
+  size_t n = 0;
+  for (const Lane& L : s->lanes) n += L.held;
+  s->admitted = n;
+  s->peak_admitted = std::max(s->peak_admitted, n);
+}
+
+// Frees an idle lane's buffers and encoder workspace (HIP executor), so that its device memory
+// no longer counts against the budget.
+int release_lane(fv_server* s, Lane& L) {
+  if (s->cfg.executor != FV_EXEC_HIP) {
+    L.held = 0;
+    return FV_OK;
+  }
+  int rc = fv_stream_release(s->gmm->device, L.stream);
+  if (L.dX && hipFree(L.dX) != hipSuccess) rc = FV_E_DEVICE;
+  if (L.dOut && hipFree(L.dOut) != hipSuccess) rc = FV_E_DEVICE;
+  L.dX = L.dOut = nullptr;
+  L.dX_cap = L.dOut_cap = 0;
+  L.caps = fv::BatchCaps{};
+  L.ws_bytes = 0;
+  L.held = 0;
+  return rc;
 }
 
 void finish_request(fv_server* s, Request* r, int status, double t) {
@@ -184,24 +237,31 @@ int launch(fv_server* s, Lane& L) {
   const int B = (int)L.batch.size();
   std::vector<int64_t> off((size_t)B + 1, 0);
   for (int b = 0; b < B; ++b) off[b + 1] = off[b] + L.batch[b]->rows;
-  const size_t need_x = (size_t)off[B] * D, need_o = (size_t)B * s->out_len;
-  if (need_x > L.dX_cap) {
+  // grow the lane to exactly what admission counted for this batch
+  if (L.need_x > L.dX_cap) {
     if (L.dX) {
       if (hipStreamSynchronize(L.stream) != hipSuccess || hipFree(L.dX) != hipSuccess) return FV_E_DEVICE;
       L.dX = nullptr;
+      L.dX_cap = 0;
     }
-    const size_t cap = std::max<size_t>(need_x, (size_t)s->cfg.max_batch_rows * D);
-    if (hipMalloc(&L.dX, cap * 4) != hipSuccess) return FV_E_NOMEM;
-    L.dX_cap = cap;
+    if (hipMalloc(&L.dX, L.need_x * 4) != hipSuccess) return FV_E_NOMEM;
+    L.dX_cap = L.need_x;
   }
-  if (need_o > L.dOut_cap) {
+  if (L.need_o > L.dOut_cap) {
     if (L.dOut) {
       if (hipStreamSynchronize(L.stream) != hipSuccess || hipFree(L.dOut) != hipSuccess) return FV_E_DEVICE;
       L.dOut = nullptr;
+      L.dOut_cap = 0;
     }
-    const size_t cap = std::max<size_t>(need_o, (size_t)s->cfg.max_batch_frames * s->out_len);
-    if (hipMalloc(&L.dOut, cap * 4) != hipSuccess) return FV_E_NOMEM;
-    L.dOut_cap = cap;
+    if (hipMalloc(&L.dOut, L.need_o * 4) != hipSuccess) return FV_E_NOMEM;
+    L.dOut_cap = L.need_o;
+  }
+  if (!(L.need_caps == L.caps) || L.ws_bytes == 0) {
+    size_t wb = 0;
+    const int rc = fv::batch_reserve(s->gmm, s->cfg.precision, L.stream, L.need_caps, &wb);
+    if (rc != FV_OK) return rc;
+    L.caps = L.need_caps;
+    L.ws_bytes = wb;
   }
   for (int b = 0; b < B; ++b) {
     const Request* r = L.batch[b];
@@ -249,7 +309,10 @@ void scheduler(fv_server* s) {
         continue;
       }
       for (Request* r : L.batch) finish_request(s, r, st == 1 ? FV_OK : st, t);
-      s->admitted -= L.bytes;
+      if (s->cfg.executor != FV_EXEC_HIP) {  // the fake executor holds nothing between batches
+        L.held = 0;
+        update_admitted(s);
+      }
       L.batch.clear();
       L.busy = false;
       s->cv_done.notify_all();
@@ -280,32 +343,75 @@ void scheduler(fv_server* s) {
           age < s->cfg.batch_window_us)
         window_left_us = s->cfg.batch_window_us - age;
     }
-    for (Lane& L : s->lanes) {
-      if (window_left_us > 0) break;
-      if (L.busy || s->queue.empty()) continue;
+    // idle lanes, those holding the most device memory first (their buffers are reused)
+    std::vector<Lane*> order;
+    for (Lane& L : s->lanes)
+      if (!L.busy) order.push_back(&L);
+    std::stable_sort(order.begin(), order.end(),
+                     [](const Lane* a, const Lane* b) { return a->held > b->held; });
+    const size_t budget = s->cfg.hbm_budget_bytes;
+    for (Lane* Lp : order) {
+      Lane& L = *Lp;
+      if (window_left_us > 0 || s->queue.empty()) break;
       std::vector<int64_t> sizes;
       int64_t rows = 0;
-      size_t bytes = 0;
-      while (!s->queue.empty() && (int)sizes.size() < s->cfg.max_batch_frames) {
-        Request* r = s->queue.front();
-        if (!sizes.empty() && rows + r->rows > s->cfg.max_batch_rows) break;
-        sizes.push_back(r->rows);
-        const size_t nb = footprint(s, sizes);
-        if (s->cfg.hbm_budget_bytes > 0 && s->admitted + nb > s->cfg.hbm_budget_bytes) {
-          sizes.pop_back();
-          break;
+      Need need;
+      for (int attempt = 0; attempt < 2 && L.batch.empty(); ++attempt) {
+        sizes.clear();
+        rows = 0;
+        while (!s->queue.empty() && (int)sizes.size() < s->cfg.max_batch_frames) {
+          Request* r = s->queue.front();
+          if (!sizes.empty() && rows + r->rows > s->cfg.max_batch_rows) break;
+          sizes.push_back(r->rows);
+          const Need n = lane_need(s, L, sizes);
+          if (budget > 0 && held_by_others(s, L) + n.bytes > budget) {
+            sizes.pop_back();
+            break;
+          }
+          need = n;
+          rows += r->rows;
+          s->queue.pop_front();
+          r->t_admit = t;
+          L.batch.push_back(r);
         }
-        bytes = nb;
-        rows += r->rows;
-        s->queue.pop_front();
-        r->t_admit = t;
-        L.batch.push_back(r);
+        if (!L.batch.empty() || attempt > 0) break;
+        // The head does not fit beside what the lanes hold: free the other idle lanes' memory,
+        // or this lane's own when nothing else is held and nothing runs; then try once more.
+        std::vector<Lane*> victims;
+        bool running = false;
+        for (Lane& M : s->lanes) {
+          running |= M.busy;
+          if (&M != &L && !M.busy && M.held > 0) victims.push_back(&M);
+        }
+        if (victims.empty() && !running && L.held > 0) victims.push_back(&L);
+        if (victims.empty()) break;
+        for (Lane* M : victims) M->busy = true;  // nothing else takes them meanwhile
+        lk.unlock();
+        for (Lane* M : victims) (void)release_lane(s, *M);
+        lk.lock();
+        for (Lane* M : victims) M->busy = false;
+        update_admitted(s);
       }
-      if (L.batch.empty()) break;  // the head does not fit yet: keep arrival order
+      if (L.batch.empty()) {
+        bool running = false;
+        for (Lane& M : s->lanes) running |= M.busy;
+        if (!running && !s->queue.empty() && budget > 0) {
+          // nothing holds memory and nothing runs, yet the head does not fit: it never will
+          Request* r = s->queue.front();
+          s->queue.pop_front();
+          ++s->rejected;
+          finish_request(s, r, FV_E_BUDGET, t);
+          s->cv_done.notify_all();
+          launched = true;
+        }
+        break;  // keep arrival order
+      }
       L.busy = true;
-      L.bytes = bytes;
-      s->admitted += bytes;
-      s->peak_admitted = std::max(s->peak_admitted, s->admitted);
+      L.held = need.bytes;
+      L.need_x = need.x;
+      L.need_o = need.o;
+      L.need_caps = need.caps;
+      update_admitted(s);
       ++s->launches;
       for (Request* r : L.batch) r->batch_frames = (int)L.batch.size();
       if (s->busy_since < 0) s->busy_since = t;
@@ -313,15 +419,21 @@ void scheduler(fv_server* s) {
       const int rc = launch(s, L);
       const double ts = s->now_us();
       lk.lock();
+      if (s->cfg.executor == FV_EXEC_HIP) {
+        L.held = (L.dX_cap + L.dOut_cap) * 4 + L.ws_bytes;  // what the lane really holds
+        update_admitted(s);
+      }
       for (Request* r : L.batch) r->t_start = ts;
       if (rc != FV_OK) {  // this batch fails; other requests continue
         if (s->cfg.executor == FV_EXEC_HIP) {
           lk.unlock();
           (void)hipStreamSynchronize(L.stream);  // no copy may still touch the staging blocks
           lk.lock();
+        } else {
+          L.held = 0;
+          update_admitted(s);
         }
         for (Request* r : L.batch) finish_request(s, r, rc, ts);
-        s->admitted -= L.bytes;
         L.batch.clear();
         L.busy = false;
         s->cv_done.notify_all();
@@ -454,7 +566,7 @@ int submit_impl(fv_server* s, const float* X, int64_t N, uint64_t* ticket, bool 
   if (!s || !ticket || N < 0 || (N > 0 && !X)) return FV_E_INVAL;
   if (N > ((int64_t)1 << 40) / s->D) return FV_E_UNSUPPORTED;  // the encoder's row limit
   const std::vector<int64_t> one{N};
-  if (s->cfg.hbm_budget_bytes > 0 && footprint(s, one) > s->cfg.hbm_budget_bytes) {
+  if (s->cfg.hbm_budget_bytes > 0 && lane_need(s, Lane{}, one).bytes > s->cfg.hbm_budget_bytes) {
     std::lock_guard<std::mutex> lk(s->mu);
     ++s->rejected;
     return FV_E_BUDGET;
@@ -597,6 +709,16 @@ int fv_server_get_stats(fv_server* s, fv_server_stats* st, int reset) {
   if (s->busy_since >= 0) busy += (s->now_us() - s->busy_since) * 1e-6;
   st->busy_s = busy;
   st->cancelled = s->cancelled;
+  st->graph_captures = 0;
+  st->graph_replays = 0;
+  if (s->cfg.executor == FV_EXEC_HIP) {
+    for (const Lane& L : s->lanes) {
+      int64_t c = 0, r = 0;
+      fv::stream_graph_counts(s->gmm->device, L.stream, &c, &r);
+      st->graph_captures += c;
+      st->graph_replays += r;
+    }
+  }
   if (reset) {
     s->submitted = s->completed = s->failed = s->rejected = s->launches = s->rows_done = 0;
     s->cancelled = 0;

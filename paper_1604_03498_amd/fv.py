@@ -27,7 +27,8 @@ EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "f
                     "fv_server_get_stats", "fv_strerror", "fv_last_device_error",
                     "fv_pca_load", "fv_pca_free", "fv_pca_info", "fv_project",
                     "fv_encode_projected", "fv_encode_batch_projected", "fv_em_step",
-                    "fv_stream_release", "fv_dsift_rows", "fv_dsift", "fv_encode_images")
+                    "fv_stream_release", "fv_dsift_rows", "fv_dsift", "fv_encode_images",
+                    "fv_graph_counters")
 EXEC_HIP, EXEC_FAKE = 0, 1
 
 
@@ -59,7 +60,8 @@ class ServerStats(ctypes.Structure):
                 ("queued", ctypes.c_int), ("in_flight", ctypes.c_int),
                 ("admitted_bytes", ctypes.c_size_t), ("peak_admitted_bytes", ctypes.c_size_t),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
-                ("busy_s", ctypes.c_double), ("cancelled", ctypes.c_int64)]
+                ("busy_s", ctypes.c_double), ("cancelled", ctypes.c_int64),
+                ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64)]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfv.so")
@@ -128,6 +130,8 @@ def load():
     lib.fv_em_step.argtypes = [vp, vp, i64, i32, ctypes.c_float, u32, vp, vp, vp, vp,
                                ctypes.POINTER(ctypes.c_double)]
     lib.fv_stream_release.argtypes = [i32, vp]
+    lib.fv_graph_counters.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.fv_graph_counters.restype = i32
     lib.fv_dsift_rows.argtypes = [i32, i32, i32, vp, i32, i32, ctypes.POINTER(i64)]
     lib.fv_dsift.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, vp, u32, i32, vp]
     lib.fv_encode_images.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, i32, i32, vp, i32, u32,
@@ -142,6 +146,13 @@ def load():
         f.restype = i32
     _lib = lib
     return lib
+
+
+def graph_counters():
+    """fv_graph_counters: (captures, replays) of the library's launch graphs so far."""
+    c, r = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().fv_graph_counters(ctypes.byref(c), ctypes.byref(r)), "fv_graph_counters")
+    return int(c.value), int(r.value)
 
 
 def strerror(code: int) -> str:
@@ -484,9 +495,9 @@ def _marshal_images(images, device: int):
 
 
 def dsift(images, scales=None, n_scales: int = 8, bin: int = 4, step: int = 4, device: int = 0,
-          out=None, stream=None):
+          out=None, stream=None, flags: int = 0):
     """fv_dsift: [n, H, W] (or [H, W]) float32 images -> [n, rows, 130] descriptors (a device
-    tensor for device images, a host array for host images)."""
+    tensor for device images, a host array for host images); flags may add ASYNC."""
     ip, n, H, W, idev, _ki = _marshal_images(images, device)
     ns, sp, _ks = _scales_arg(scales, n_scales)
     rows = dsift_rows(H, W, scales, n_scales, bin, step)
@@ -505,7 +516,7 @@ def dsift(images, scales=None, n_scales: int = 8, bin: int = 4, step: int = 4, d
         if out.dtype != np.float32 or out.shape != shape or not out.flags.c_contiguous:
             raise ValueError(f"out must be a contiguous float32 array of shape {shape}")
         op, odev = out.ctypes.data, False
-    f = (X_DEVICE if idev else 0) | (OUT_DEVICE if odev else 0)
+    f = (X_DEVICE if idev else 0) | (OUT_DEVICE if odev else 0) | (int(flags) & ASYNC)
     s = _stream_handle(stream, device) if (idev or odev or stream is not None) else 0
     _check(load().fv_dsift(ctypes.c_void_p(ip), int(n), int(H), int(W), ns, ctypes.c_void_p(sp),
                            int(bin), int(step), ctypes.c_void_p(op), f, int(device),

@@ -77,6 +77,58 @@ def test_batch_replays_with_new_table(fv, monkeypatch):
             assert np.array_equal(out.cpu().numpy(), direct[i]), (rep, i)
 
 
+@pytest.mark.parametrize("K,D,prec", [(256, 64, 0), (256, 64, 1), (512, 80, 1), (512, 80, 0)],
+                         ids=["fused_fp32", "fused_bf16s", "twopass_bf16s", "twopass_fp32"])
+def test_batch_graph_serves_every_shape(fv, K, D, prec, monkeypatch):
+    """Batches of different frame counts, sizes and chunk counts on one stream share one
+    captured graph (the kernels read the batch's sizes from the work table; the grids depend
+    on the stream's capacities only): after the first batch sets the capacities, no batch
+    that fits them captures again, and every replay equals the eager (uncaptured) encode
+    bitwise, with eager work between the replays."""
+    import torch
+    say(f"[gpu] shape-independent batch graph K={K} D={D} prec={prec}")
+    g = fvsynth.gmm(K, D, 1)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    shapes = [[9000, 7000, 4000, 3000, 1000, 2500, 777, 33],  # largest first: sets the capacities
+              [1, 0, 5000], [1100], [2000, 2000, 2000, 2000, 2000], [0], [4096, 1024, 3000],
+              [31, 32, 33, 1023, 1024, 1025]]
+    rows_max = max(sum(s) for s in shapes)
+    data = [fvsynth.batch_frames(g, s, seed0=300 + 10 * i) for i, s in enumerate(shapes)]
+    stream = torch.cuda.Stream()
+    Xd = torch.zeros(rows_max, D, device="cuda")
+    out = torch.zeros(8, 2 * K * D, device="cuda")
+    monkeypatch.setenv("FV_GRAPH", "0")
+    direct = []
+    for X, off in data:
+        Xd[:X.shape[0]].copy_(torch.from_numpy(X))
+        B = off.size - 1
+        direct.append(fv.encode_batch(h, Xd[:X.shape[0]], off, out=out[:B].clone(),
+                                      precision=prec, stream=stream).cpu().numpy())
+    monkeypatch.setenv("FV_GRAPH", "1")
+    c0 = None
+    captured_by = []
+    for rep in range(2):
+        for i, (X, off) in enumerate(data):
+            B = off.size - 1
+            Xd[:X.shape[0]].copy_(torch.from_numpy(X))
+            torch.cuda.synchronize()
+            cb = fv.graph_counters()[0]
+            fv.encode_batch(h, Xd[:X.shape[0]], off, out=out[:B], precision=prec,
+                            flags=fv.ASYNC, stream=stream)
+            stream.synchronize()
+            assert np.array_equal(out[:B].cpu().numpy(), direct[i]), (rep, i)
+            _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+            if c0 is None:
+                c0 = fv.graph_counters()[0]   # after the first batch's capture
+            elif fv.graph_counters()[0] != cb:
+                captured_by.append((rep, shapes[i]))
+    c1, r1 = fv.graph_counters()
+    say(f"  captures after the first batch: {c1 - c0} {captured_by}; replays so far {r1}")
+    assert c1 == c0, captured_by
+    fv.stream_release(stream)
+    h.free()
+
+
 def test_reloaded_models_do_not_replay_stale_graphs(fv, monkeypatch):
     """Captured sequences are keyed by the handle's load serial, not its address: a model
     loaded after another was freed (its handle may land at the freed address, its constants

@@ -281,3 +281,28 @@ def test_non_finite_descriptor_propagates(fv):
     outb = fv.encode_batch(h, Xb, np.array([0, 300, 600], np.int64))
     assert np.array_equal(outb[0], fv.encode_batch(h, X, np.array([0, 300], np.int64))[0])
     assert np.all(np.isfinite(outb[0])) and np.all(outb[1] == 0)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp32", "bf16_split", "fp16_split"])
+@pytest.mark.parametrize("path", ["fused", "split"])
+def test_non_finite_descriptor_propagates_every_form(fv, prec, path, monkeypatch):
+    """The same for every form and both paths at K = 256 (the fused kernels at one component
+    group, and the batch): a NaN descriptor makes its frame's raw vector NaN and its normalised
+    vector zero, and leaves the other frames of the batch as they are alone."""
+    monkeypatch.setenv("FV_PATH", path)
+    say(f"[gpu] NaN propagation {prec} {path}")
+    g = fvsynth.gmm(256, 64, 0)
+    h = _gmm(fv, g)
+    X = fvsynth.frame(g, 3000, 3, 0.05)
+    Xn = X.copy()
+    Xn[1700, 5] = np.nan
+    raw = fv.encode(h, Xn, precision=prec, flags=fv.NO_POWER_NORM | fv.NO_L2_NORM)
+    assert np.all(np.isnan(raw))
+    assert np.all(fv.encode(h, Xn, precision=prec) == 0)
+    Xb = np.concatenate([X, Xn, X[:1000]])
+    off = np.array([0, 3000, 6000, 7000], np.int64)
+    outb = fv.encode_batch(h, Xb, off, precision=prec)
+    alone = fv.encode_batch(h, np.concatenate([X, X[:1000]]), np.array([0, 3000, 4000], np.int64),
+                            precision=prec)
+    assert np.array_equal(outb[0], alone[0]) and np.array_equal(outb[2], alone[1])
+    assert np.all(outb[1] == 0)

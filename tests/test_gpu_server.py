@@ -110,6 +110,59 @@ def test_small_budget_forces_queueing(fv):
         assert e["e_inf"] <= 1e-5 and e["e_2"] <= 1e-5
 
 
+def test_budget_bounds_device_memory(fv):
+    """The budget bounds the device memory the server holds (its lanes' buffers and encoder
+    workspaces, kept between launches): the drop of the device's free memory while serving a
+    mix of the serving shape's frames stays within the budget plus a fixed overhead of 16 MiB
+    (streams, events, executable graphs, runtime pools), and the memory comes back when the
+    server is destroyed."""
+    import threading
+    import torch
+    say("[gpu] server device memory within the budget, K=512 D=80 bf16 split")
+    g = fvsynth.gmm(512, 80, 0)
+    sizes = [8000, 32000, 12500, 24500, 18000, 8000, 32000, 12500]
+    frames = [fvsynth.frame(g, n, 1300 + i, 0.05) for i, n in enumerate(sizes)]
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    budget = 64 << 20
+    overhead = 16 << 20
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    low = [free0]
+    stop = threading.Event()
+
+    def sample():
+        while not stop.is_set():
+            low[0] = min(low[0], torch.cuda.mem_get_info()[0])
+            time.sleep(0.001)
+
+    th = threading.Thread(target=sample, daemon=True)
+    th.start()
+    try:
+        cfg = fv.server_config(precision=fv.PREC_BF16_SPLIT, n_streams=2, hbm_budget_bytes=budget)
+        with fv.Server(h, cfg) as s:
+            tickets = [s.submit(X) for X in frames] + [s.submit(X) for X in frames[::-1]]
+            res = drain(s, tickets)
+            st = s.stats()
+            low[0] = min(low[0], torch.cuda.mem_get_info()[0])
+    finally:
+        stop.set()
+        th.join()
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    drop = free0 - low[0]
+    say(f"  held peak {st['peak_admitted_bytes'] / 2**20:.1f} MiB, device free-memory drop "
+        f"{drop / 2**20:.1f} MiB (budget 64 MiB + 16 MiB), after destroy {(free0 - free1) / 2**20:.1f} MiB")
+    assert st["peak_admitted_bytes"] <= budget
+    assert drop <= budget + overhead
+    assert free0 - free1 <= overhead
+    for i, t in enumerate(tickets):
+        assert res[t][0] == fv.OK, (i, res[t][0])
+    ref = oracle.encode_gmm(frames[1], g)
+    e = errors(res[tickets[1]][1], ref)
+    assert e["e_inf"] <= 1e-3 and e["e_2"] <= 1e-3
+    h.free()
+
+
 def test_device_submission_matches_host_submission(fv):
     import torch
     say("[gpu] server device-resident frames, bf16 split K=512 D=80")
