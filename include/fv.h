@@ -120,6 +120,28 @@ int fv_encode(const fv_gmm* gmm, const float* X, int64_t N, float* out, int prec
               unsigned flags, void* hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): fv_encode with every intermediate in one fixed
+ * scratch array per GPU of FV_NOALLOC_SCRATCH_BYTES bytes, which the library's code object
+ * holds on each GPU it runs on from load until the process ends.  X and out must be device
+ * memory (FV_X_DEVICE and FV_OUT_DEVICE set, else FV_E_INVAL).  The call allocates nothing,
+ * captures no graph and records no event.  A frame whose intermediates do not fit fails with
+ * FV_E_UNSUPPORTED before anything is launched.  The per-chunk partial statistics are
+ * bounded (at most one chunk per resident workgroup: about 34 MB at K = 256, D = 64 and 22 MB at
+ * K = 512, D = 80); beyond them the intermediates grow with N only through the two-pass path's
+ * per-row normalisers (8 bytes per row and group of 256 components), so frames up to about 2.8
+ * million rows fit at K = 512, D = 80, and any N at K <= 256, D <= 64.  Within the limit the result is the one of fv_encode with the same kernels (the
+ * two-pass path and the E-step recompute stand in where the preferred plan would not fit).
+ * Every call on a GPU uses the same scratch: calls that overlap in time on one GPU (other
+ * streams, other threads) race and give wrong results, so serialise them; FV_ASYNC calls on
+ * one stream are ordered and safe.  The scratch keeps the last call's contents; no part of it
+ * needs to start at zero (every intermediate is written before it is read).
+ */
+#define FV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fv_encode_noalloc(const fv_gmm* gmm, const float* X, int64_t N, float* out, int precision,
+                      unsigned flags, void* hip_stream);
+
+/*
  * Encode B frames in one launch sequence.  Frame b is rows [offsets[b], offsets[b+1]) of
  * X [offsets[B] x D]; out is [B x 2*K*D].  `offsets` is a HOST array of B+1 int64 values
  * with offsets[0] == 0 and offsets non-decreasing (else FV_E_INVAL).  Frames are split into

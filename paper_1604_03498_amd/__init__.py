@@ -13,5 +13,5 @@ from .fv import (  # noqa: F401
     EXEC_FAKE, Server, ServerConfig,
     server_config, set_tuning, get_tuning, Tuning, Pca, pca_load, project, encode_projected,
     encode_batch_projected, em_step, em_fit, stream_release, DSIFT_DIM, dsift_rows, dsift,
-    encode_images, graph_counters,
+    encode_images, encode_noalloc, graph_counters,
 )

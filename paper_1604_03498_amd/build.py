@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfv.so")
 
 SOURCES = ["fv_api.cpp", "fv_server.cpp", "fv_kernels.hip", "fv_split.hip", "fv_finalize.hip",
-           "fv_dsift.hip", "fv_dsift_host.cpp",
+           "fv_dsift.hip", "fv_dsift_host.cpp", "fv_noalloc.hip",
            "fv_form_bf16s.hip", "fv_form_f16s.hip", "fv_form_bf16.hip", "fv_project.hip",
            "fv_em.hip"]
 # Statistics kernels built without NaN-preserving max semantics: every fmaxf of an MFMA or

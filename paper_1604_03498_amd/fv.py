@@ -28,7 +28,7 @@ EXPORTED_SYMBOLS = ("fv_limits", "fv_gmm_load", "fv_gmm_free", "fv_gmm_info", "f
                     "fv_pca_load", "fv_pca_free", "fv_pca_info", "fv_project",
                     "fv_encode_projected", "fv_encode_batch_projected", "fv_em_step",
                     "fv_stream_release", "fv_dsift_rows", "fv_dsift", "fv_encode_images",
-                    "fv_graph_counters")
+                    "fv_encode_noalloc", "fv_graph_counters")
 EXEC_HIP, EXEC_FAKE = 0, 1
 
 
@@ -97,6 +97,8 @@ def load():
     lib.fv_gmm_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.fv_encode.argtypes = [vp, vp, i64, vp, i32, u32, vp]
     lib.fv_encode_batch.argtypes = [vp, vp, vp, i32, vp, i32, u32, vp]
+    lib.fv_encode_noalloc.argtypes = [vp, vp, i64, vp, i32, u32, vp]
+    lib.fv_encode_noalloc.restype = i32
     lib.fv_pca_load.argtypes = [i32, i32, vp, vp, i32, ctypes.POINTER(vp)]
     lib.fv_pca_free.argtypes = [vp]
     lib.fv_pca_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -329,6 +331,24 @@ def encode(g: Gmm, X, out=None, precision: int = PREC_FP32, flags: int = 0, stre
     rc = load().fv_encode(ctypes.c_void_p(g.handle), ctypes.c_void_p(xp), int(n),
                           ctypes.c_void_p(op), int(precision), f, ctypes.c_void_p(s))
     _check(rc, "fv_encode")
+    return out
+
+
+def encode_noalloc(g: Gmm, X, out=None, precision: int = PREC_FP32, flags: int = 0,
+                   stream=None):
+    """fv_encode_noalloc: fv_encode on the library's fixed per-GPU scratch (no allocation);
+    X and out must be device tensors."""
+    xp, n, xdev, _keep = _marshal_x(g, X)
+    if not xdev:
+        raise ValueError("encode_noalloc needs X in device memory")
+    out, op, odev = _marshal_out(g, out, None, True)
+    if not odev:
+        raise ValueError("encode_noalloc needs out in device memory")
+    f = (int(flags) & ~(X_DEVICE | OUT_DEVICE)) | X_DEVICE | OUT_DEVICE
+    s = _stream_handle(stream, g.device)
+    _check(load().fv_encode_noalloc(ctypes.c_void_p(g.handle), ctypes.c_void_p(xp), int(n),
+                                    ctypes.c_void_p(op), int(precision), f, ctypes.c_void_p(s)),
+           "fv_encode_noalloc")
     return out
 
 
