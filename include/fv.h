@@ -337,6 +337,9 @@ typedef struct fv_server_config {
   int fake_K, fake_D;       /* FV_EXEC_FAKE only: output size 2*K*D when gmm is NULL */
   double fake_us_per_krow;  /* FV_EXEC_FAKE only */
   int fake_fail_every;      /* FV_EXEC_FAKE only: every n-th batch fails with FV_E_DEVICE */
+  int copy_threads;         /* helper threads that share the submit-side copy of a host frame of
+                               2 MiB or more into its pinned staging (0: the submitting thread
+                               copies alone; default 3; at most 16) */
 } fv_server_config;
 
 typedef struct fv_req_stats {

@@ -44,7 +44,8 @@ class ServerConfig(ctypes.Structure):
                 ("deadline_ms", ctypes.c_double), ("batch_window_us", ctypes.c_double),
                 ("executor", ctypes.c_int),
                 ("fake_K", ctypes.c_int), ("fake_D", ctypes.c_int),
-                ("fake_us_per_krow", ctypes.c_double), ("fake_fail_every", ctypes.c_int)]
+                ("fake_us_per_krow", ctypes.c_double), ("fake_fail_every", ctypes.c_int),
+                ("copy_threads", ctypes.c_int)]
 
 
 class ReqStats(ctypes.Structure):
