@@ -245,6 +245,21 @@ def time_form(fv, torch, h, Xd, off, out, form, steps, warmup, stream, lat_sampl
     return elapsed, st_ms / max(st_n, 1), st_n, fi_ms / max(fi_n, 1), np.array(lat)
 
 
+def trial_name(t):
+    n = f"{'fused' if t['batch_path'] == 1 else 'split'}/{t['batch_chunk']}"
+    if t.get("batch_grid"):
+        n += f"/grid{t['batch_grid']}"
+    if t.get("fused16_variant"):
+        n += f"/v{t['fused16_variant']}"
+    return n
+
+
+def apply_tuned(fv, h, tuned):
+    """The autotuner's choice for a form, recorded in the batch results."""
+    fv.set_tuning(h, batch_path=1 if tuned["path"] == "fused" else 2, batch_chunk=tuned["chunk"],
+                  batch_grid=tuned.get("grid", 0), fused16_variant=tuned.get("variant", 0))
+
+
 def time_steps(torch, step, steps, warmup, stream):
     """`warmup` untimed steps, then `steps` timed ones with a HIP event recorded on `stream`
     before the first and after every step; the region is bracketed by device
@@ -520,6 +535,7 @@ def main():
                                         use_cache=False)
         bpath = {1: "fused", 2: "split"}[tuned["batch_path"]]
         log(f"[bench] batch form={form} tuned path={bpath} chunk={tuned['batch_chunk']} "
+            f"grid={tuned.get('batch_grid', 0)} variant={tuned.get('fused16_variant', 0)} "
             f"warmup={a.warmup} steps={a.steps}")
 
         def bstep(prec=prec, outb=outb):
@@ -534,8 +550,10 @@ def main():
                        "wall_ms_per_step": wall * 1e3 / a.steps, "roofline": rf,
                        "finalize_avg_us": round(fi_avg * 1e3, 3), "stats_launches": st_n,
                        "tuned": {"path": bpath, "chunk": tuned["batch_chunk"],
-                                 "trials_ms": {f"{'fused' if t['batch_path'] == 1 else 'split'}/{t['batch_chunk']}":
-                                               round(t["ms"], 4) for t in tuned["trials"]}}}
+                                 "grid": tuned.get("batch_grid", 0),
+                                 "variant": tuned.get("fused16_variant", 0),
+                                 "trials_ms": {trial_name(t): round(t["ms"], 4)
+                                               for t in tuned["trials"]}}}
         batch_out[form] = outb.cpu().numpy()
         log(f"[bench]   {batch[form]['value']:.4e} desc/s, {ms:.4f} ms/step (median "
             f"{batch[form]['step_ms']['median']:.4f}), stats kernel {rf['kernel_avg_us']} us, "
@@ -615,8 +633,7 @@ def main():
                     f"stats {st_avg * 1e3:.3f} us")
             if batch and form in batch:
                 outb = torch.empty(offb.size - 1, 2 * K * D, dtype=torch.float32, device=dev)
-                fv.set_tuning(hb, batch_path=1 if batch[form]["tuned"]["path"] == "fused" else 2,
-                              batch_chunk=batch[form]["tuned"]["chunk"])
+                apply_tuned(fv, hb, batch[form]["tuned"])
                 for name, xin in (("batch", Xbd), ("batch_clustered", Xbcd)):
                     el, st_avg, _, _, _ = time_form(fv, torch, hb, xin, offb, outb, form,
                                                     a.batch_steps, 2, stream, 0, True,
@@ -654,8 +671,7 @@ def main():
                 out = torch.empty(shape, dtype=torch.float32, device=dev)
                 prec = PREC_CODE[form]
                 if offr is not None and form in batch:
-                    fv.set_tuning(hb, batch_path=1 if batch[form]["tuned"]["path"] == "fused" else 2,
-                                  batch_chunk=batch[form]["tuned"]["chunk"])
+                    apply_tuned(fv, hb, batch[form]["tuned"])
 
                 def pstep():
                     if offr is None:
@@ -875,5 +891,25 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def reap_children():
+    """Nothing this run started may outlive it: name any child process still running (on
+    stderr), then end it by its pid."""
+    try:
+        import psutil
+    except ImportError:
+        return
+    kids = psutil.Process().children(recursive=True)
+    for k in kids:
+        try:
+            log(f"child process still running at exit: pid {k.pid} {' '.join(k.cmdline())[:120]}")
+            k.terminate()
+        except psutil.Error:
+            pass
+    psutil.wait_procs(kids, timeout=5)
+
+
 if __name__ == "__main__":
-    main()
+    try:
+        main()
+    finally:
+        reap_children()

@@ -159,12 +159,20 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
  *   batch_path          0 = automatic (fused single pass when K <= 256), 1 = fused, 2 = two-pass
  *   single_split_below  fv_encode takes the two-pass path for N below this (0 = automatic:
  *                       four 32-row tiles per resident workgroup)
+ *   batch_grid          workgroups of fv_encode_batch's statistics launch (the fused kernel or
+ *                       the first pass; 0 = automatic: the resident workgroup count); the
+ *                       kernels loop over the work items, so results do not depend on it
+ *   fused16_variant     fused 16-bit kernel at 256 components, DP <= 64: 0 = automatic (the
+ *                       wave-specialised kernel), 1 = wave-specialised, 2 = single-role
+ *                       (transposed E-step); results agree within rounding
  * Not synchronised with encodes running concurrently on the same handle.  Errors: FV_E_INVAL.
  */
 typedef struct fv_tuning {
   int batch_chunk;
   int batch_path;
   int64_t single_split_below;
+  int batch_grid;
+  int fused16_variant;
 } fv_tuning;
 
 int fv_gmm_set_tuning(fv_gmm* gmm, const fv_tuning* tuning); /* NULL restores the defaults */
@@ -178,6 +186,9 @@ int fv_gmm_get_tuning(const fv_gmm* gmm, fv_tuning* tuning);
  *   FV_GRAPH=0            never capture or replay graphs
  *   FV_SPLIT_GAMMA=0      FP32 two-pass frames recompute the E-step in the second pass instead
  *                         of reading the posterior factors the first pass wrote
+ *   FV_MAX_GRID=n         cap the first grid dimension of every statistics launch at n
+ *   FV_FUSED16=t          the single-role fused 16-bit kernel instead of the wave-specialised
+ *                         one
  */
 
 /*
@@ -279,8 +290,9 @@ int fv_dsift(const float* images, int n_images, int H, int W, int n_scales,
              void* hip_stream);
 
 /* Fisher vector of each image: fv_dsift (into the library's scratch), the projection `pca`
- * (Din = FV_DSIFT_DIM, D = the GMM's D), then the batched encode with image n as frame n;
- * out [n_images x 2KD].  Images on the host (copied in) or device (FV_X_DEVICE); out per
+ * (Din = FV_DSIFT_DIM, D = the GMM's D), then the batched encode with image n as frame n, or,
+ * when the images have too few rows to fill the GPU's resident workgroups in batch chunks, an
+ * fv_encode of each image (the same vectors within rounding); out [n_images x 2KD].  Images on the host (copied in) or device (FV_X_DEVICE); out per
  * FV_OUT_DEVICE; other flags and errors as fv_encode_batch and fv_dsift. */
 int fv_encode_images(const fv_gmm* gmm, const fv_pca* pca, const float* images, int n_images,
                      int H, int W, int n_scales, const double* scales, int bin, int step,

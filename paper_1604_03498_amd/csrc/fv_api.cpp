@@ -35,6 +35,7 @@ constexpr unsigned kGraphFlags = FV_NO_POWER_NORM | FV_NO_L2_NORM | FV_THRESHOLD
 fv::Consts call_consts(const fv_gmm* g, unsigned flags) {
   fv::Consts c = g->c;
   c.thresh = (flags & FV_THRESHOLD) ? 1 : 0;
+  c.variant16 = g->fused16_variant;
   return c;
 }
 
@@ -101,9 +102,10 @@ struct GraphKey {
   const void* pinned = nullptr;
   uint64_t pca = 0;  // 0: no projection
   int cap = 0;       // FV_MAX_GRID in force at capture (0: none)
+  int grid = 0, variant = 0;  // the handle's batch_grid and fused16_variant tuning
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && gmm == o.gmm && precision == o.precision && flags == o.flags &&
-           cap == o.cap &&
+           cap == o.cap && grid == o.grid && variant == o.variant &&
            path == o.path && P == o.P && rows == o.rows && B == o.B && n_items == o.n_items &&
            n_groups == o.n_groups && X == o.X && out == o.out && dev == o.dev &&
            pinned == o.pinned && pca == o.pca;
@@ -356,6 +358,12 @@ int grid_cap(int g) {
   return x >= 1 ? std::min(g, x) : g;
 }
 
+// FV_FUSED16=t (measurements): the single-role fused 16-bit kernel.
+bool fused16_env_single() {
+  const char* e = std::getenv("FV_FUSED16");
+  return e && e[0] == 't';
+}
+
 // Path override for tests and measurements: FV_PATH=fused|split (default: automatic).
 int path_override() {
   const char* e = std::getenv("FV_PATH");
@@ -511,9 +519,9 @@ int project_grid(int device, int64_t N) {
 // norm parts, first-pass normalisers (two-pass path), the work table (Counts record, frames,
 // items, groups), staging of host X and host out, and the projected rows.
 struct BatchLayout {
-  size_t part = 0, norm = 0, lse = 0, cnt = 0, frames = 0, items = 0, groups = 0;
+  size_t part = 0, norm = 0, lse = 0, cnt = 0, frames = 0, items = 0, groups = 0, order = 0;
   size_t x = 0, out = 0, y = 0;
-  size_t tab() const { return cnt + frames + items + groups; }
+  size_t tab() const { return cnt + frames + items + groups + order; }
   size_t total() const { return part + norm + lse + tab() + x + out + y; }
 };
 
@@ -528,6 +536,7 @@ BatchLayout batch_layout(const fv::Consts& c, Path path, const fv::BatchCaps& cp
   l.frames = align256((size_t)cp.B * sizeof(fv::Frame));
   l.items = align256((size_t)cp.items * sizeof(fv::Item));
   l.groups = align256((size_t)cp.groups * sizeof(fv::Group));
+  l.order = align256((size_t)cp.items * sizeof(int32_t));
   l.x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)cp.rows * Din * 4);
   l.out = (flags & FV_OUT_DEVICE) ? 0 : align256((size_t)cp.B * out_len * 4);
   l.y = pca ? align256((size_t)cp.rows * c.D * 4) : 0;
@@ -880,14 +889,19 @@ int fv_gmm_set_tuning(fv_gmm* gmm, const fv_tuning* t) {
     gmm->batch_chunk = 0;
     gmm->batch_path = 0;
     gmm->single_split_below = 0;
+    gmm->batch_grid = 0;
+    gmm->fused16_variant = 0;
     return FV_OK;
   }
   if (t->batch_chunk < 0 || (t->batch_chunk > 0 && t->batch_chunk < 128) || t->batch_path < 0 ||
-      t->batch_path > 2 || t->single_split_below < 0)
+      t->batch_path > 2 || t->single_split_below < 0 || t->batch_grid < 0 ||
+      t->batch_grid > (1 << 20) || t->fused16_variant < 0 || t->fused16_variant > 2)
     return FV_E_INVAL;
   gmm->batch_chunk = t->batch_chunk;
   gmm->batch_path = t->batch_path;
   gmm->single_split_below = t->single_split_below;
+  gmm->batch_grid = t->batch_grid;
+  gmm->fused16_variant = t->fused16_variant;
   return FV_OK;
 }
 
@@ -896,6 +910,8 @@ int fv_gmm_get_tuning(const fv_gmm* gmm, fv_tuning* t) {
   t->batch_chunk = gmm->batch_chunk;
   t->batch_path = gmm->batch_path;
   t->single_split_below = gmm->single_split_below;
+  t->batch_grid = gmm->batch_grid;
+  t->fused16_variant = gmm->fused16_variant;
   return FV_OK;
 }
 
@@ -1077,6 +1093,8 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
   key.dev = ws->dev;
   key.pca = pca ? pca->serial : 0;
   key.cap = grid_cap(1 << 30) == (1 << 30) ? 0 : grid_cap(1 << 30);
+  key.grid = gmm->batch_grid;
+  key.variant = gmm->fused16_variant + (fused16_env_single() ? 4 : 0);
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   if (!(flags & FV_OUT_DEVICE))
@@ -1139,7 +1157,8 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   const size_t out_len = (size_t)2 * c.K * c.D;
   const BatchLayout lay = batch_layout(c, path, cp, Din, flags, pca != nullptr);
   const size_t b_part = lay.part, b_norm = lay.norm, b_lse = lay.lse, b_cnt = lay.cnt;
-  const size_t b_frames = lay.frames, b_items = lay.items, b_tab = lay.tab();
+  const size_t b_frames = lay.frames, b_items = lay.items, b_groups = lay.groups;
+  const size_t b_tab = lay.tab();
   const size_t b_x = lay.x, b_out = lay.out, b_y = lay.y;
   int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_tab + b_x + b_out + b_y, s);
   if (rc) return rc;
@@ -1154,6 +1173,8 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   fv::Frame* dframes = reinterpret_cast<fv::Frame*>(tab + b_cnt);
   fv::Item* ditems = reinterpret_cast<fv::Item*>(tab + b_cnt + b_frames);
   fv::Group* dgroups = reinterpret_cast<fv::Group*>(tab + b_cnt + b_frames + b_items);
+  const int32_t* dorder =
+      reinterpret_cast<const int32_t*>(tab + b_cnt + b_frames + b_items + b_groups);
   float* xdev = reinterpret_cast<float*>(tab + b_tab);
   float* odev = reinterpret_cast<float*>(tab + b_tab + b_x);
   float* ydev = reinterpret_cast<float*>(tab + b_tab + b_x + b_out);
@@ -1165,6 +1186,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   fv::Frame* hframes = reinterpret_cast<fv::Frame*>(pin + b_cnt);
   fv::Item* hitems = reinterpret_cast<fv::Item*>(pin + b_cnt + b_frames);
   fv::Group* hgroups = reinterpret_cast<fv::Group*>(pin + b_cnt + b_frames + b_items);
+  int32_t* horder = reinterpret_cast<int32_t*>(pin + b_cnt + b_frames + b_items + b_groups);
   *hcounts = fv::Counts{rows, n_items, (int32_t)((rows + fv::kTile - 1) / fv::kTile), B, 0};
   std::memcpy(hframes, frames.data(), (size_t)B * sizeof(fv::Frame));
   {
@@ -1181,6 +1203,11 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
         hgroups[gi] = fv::Group{i0, ni};
       }
     }
+    // the statistics launch takes the items largest first (full chunks, then every frame's
+    // last, partial chunk by size), so the partial ones fill the end of the launch
+    for (int32_t k = 0; k < n_items; ++k) horder[k] = k;
+    std::stable_sort(horder, horder + n_items,
+                     [&](int32_t a, int32_t b) { return hitems[a].nrows > hitems[b].nrows; });
   }
   const float* Xd = X;
   if (!(flags & FV_X_DEVICE) && rows > 0) {
@@ -1193,6 +1220,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   const bool vec_ok = (c.D % 4 == 0) && ((reinterpret_cast<uintptr_t>(Fx) & 15) == 0);
   fv::Consts cc = c;
   cc.cnt = dcounts;
+  cc.queue = fv::ItemQueue{const_cast<int32_t*>(&dcounts->next), dorder};
   // The table copy, the projection (if any), one persistent statistics launch over the items
   // (grid = resident workgroups) or the two passes, then the finalize over the frame capacity
   // (slots past the batch exit at once).  Every grid depends on the capacities only.
@@ -1205,17 +1233,21 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
       timing_end(tp, 2, s);
     }
     hipEvent_t t0 = timing_begin(s);
-    const int resident = resident_fused(gmm->device, c.Wg);
+    const int resident = gmm->batch_grid > 0 ? gmm->batch_grid : resident_fused(gmm->device, c.Wg);
     if (path == Path::kFused) {
       FV_HIP(run_stats(cc, precision, Fx, vec_ok, cp.rows, P, ditems, cp.items,
                        grid_cap(resident), partials, s));
     } else {
+      // The two passes span component groups in blockIdx.y, which one counter cannot serve
+      // (and the first pass walks tiles, not the table's items): static assignment.
+      fv::Consts c2 = cc;
+      c2.queue = fv::ItemQueue{nullptr, nullptr};
       const int tiles_cap = (int)((cp.rows + fv::kTile - 1) / fv::kTile);
-      FV_HIP(run_lse(cc, precision, Fx, vec_ok, cp.rows, tiles_cap, grid_cap(resident), lse,
+      FV_HIP(run_lse(c2, precision, Fx, vec_ok, cp.rows, tiles_cap, grid_cap(resident), lse,
                      cp.rows, s));
       const int groups = normext_groups(c);
       const int grid2 = grid_cap(xcd_grid((device_cu_count(gmm->device) + groups - 1) / groups));
-      FV_HIP(run_normext(cc, precision, Fx, vec_ok, cp.rows, P, ditems, cp.items, grid2, lse,
+      FV_HIP(run_normext(c2, precision, Fx, vec_ok, cp.rows, P, ditems, cp.items, grid2, lse,
                          cp.rows, partials, s));
     }
     timing_end(t0, 0, s);
@@ -1246,6 +1278,8 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   key.pinned = ws->pinned;
   key.pca = pca ? pca->serial : 0;
   key.cap = grid_cap(1 << 30) == (1 << 30) ? 0 : grid_cap(1 << 30);
+  key.grid = gmm->batch_grid;
+  key.variant = gmm->fused16_variant + (fused16_env_single() ? 4 : 0);
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   FV_HIP(hipEventRecord(ws->pin_done, s));
@@ -1326,6 +1360,21 @@ int fv_encode_images(const fv_gmm* gmm, const fv_pca* pca, const float* images, 
   rc = fv::dsift_enqueue(*p, gmm->device, s, images, (flags & FV_X_DEVICE) != 0, n_images,
                          nullptr, &rows);
   if (rc) return rc;
+  // A few images give the batched statistics launch too few chunks to fill the resident grid
+  // (18 per 320 x 240 image): then each image is encoded on its own, with the single-frame
+  // plan, which sizes its chunks to the GPU.
+  const int64_t chunks = (p->ndesc + batch_chunk(gmm) - 1) / batch_chunk(gmm);
+  if ((int64_t)n_images * chunks < resident_fused(gmm->device, gmm->c.Wg)) {
+    const size_t out_len = (size_t)2 * gmm->K * gmm->D;
+    for (int b = 0; b < n_images; ++b) {
+      rc = encode_impl(gmm, pca, rows + (size_t)b * p->ndesc * fv::kDsiftDim, p->ndesc,
+                       out + (size_t)b * out_len, precision, (flags | FV_X_DEVICE) | FV_ASYNC,
+                       hip_stream);
+      if (rc) return rc;
+    }
+    if (!(flags & FV_ASYNC)) FV_HIP(hipStreamSynchronize(s));
+    return FV_OK;
+  }
   std::vector<int64_t> offsets((size_t)n_images + 1);
   for (int b = 0; b <= n_images; ++b) offsets[(size_t)b] = (int64_t)b * p->ndesc;
   return encode_batch_impl(gmm, pca, rows, offsets.data(), n_images, out, precision,

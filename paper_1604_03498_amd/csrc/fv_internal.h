@@ -32,8 +32,41 @@ struct Counts {
   int32_t n_items;
   int32_t n_tiles;
   int32_t B;
-  int32_t pad;
+  int32_t next;  // work-item counter of the statistics launch (0 in the table copy)
 };
+
+// Dynamic work assignment of a persistent statistics launch over a work table: a workgroup
+// draws its next item from the counter, in `order` (the table's items, largest first), so
+// that workgroups finishing early take the remaining items.  Null `next`: the static
+// assignment blockIdx.x, blockIdx.x + gridDim.x, ...  Every item's partial slot is computed
+// by one workgroup in a fixed order, so the result does not depend on the assignment.  Only a
+// launch with one row of workgroups (gridDim.y = 1) over the table's items may take a queue,
+// once per reset of the counter.
+struct ItemQueue {
+  int* next;
+  const int* order;
+};
+
+// First and next item of the calling workgroup (every thread gets the same index; n = the
+// item count).  The dynamic form draws with one thread and shares it through *s_it behind
+// barriers, so every thread of the workgroup must call these in the same sequence.
+__device__ __forceinline__ int item_draw(const ItemQueue& q, int n) {
+  const int k = atomicAdd(q.next, 1);
+  return k < n ? q.order[k] : n;
+}
+__device__ __forceinline__ int item_first(const ItemQueue& q, int n, int* s_it) {
+  if (!q.next) return blockIdx.x;
+  if (threadIdx.x == 0) *s_it = item_draw(q, n);
+  __syncthreads();
+  return *s_it;
+}
+__device__ __forceinline__ int item_next(const ItemQueue& q, int n, int* s_it, int it) {
+  if (!q.next) return it + gridDim.x;
+  __syncthreads();  // every thread has read the previous index
+  if (threadIdx.x == 0) *s_it = item_draw(q, n);
+  __syncthreads();
+  return *s_it;
+}
 
 // Loop bound of a grid-stride kernel: work items from the table (statistics chunks, or the
 // arithmetic 32-row tiles when there is no item table), else the launch argument.
@@ -78,6 +111,11 @@ struct Consts {
   int thresh;
   // Per call: the batched sequence's device-side sizes (null: the launch arguments hold them)
   const Counts* cnt;
+  // Per call: dynamic item assignment of the batched statistics launch (null next: static)
+  ItemQueue queue;
+  // Per call: fused 16-bit kernel at 256 components (0 automatic, 1 wave-specialised,
+  // 2 single-role)
+  int variant16;
 };
 
 // A chunk of consecutive descriptor rows whose statistics go to one partial slot.
@@ -326,6 +364,8 @@ struct fv_gmm {
   int batch_chunk = 0;
   int batch_path = 0;
   int64_t single_split_below = 0;
+  int batch_grid = 0;
+  int fused16_variant = 0;
 };
 
 // Status of an arithmetic form for this model: FV_OK, FV_E_INVAL for an unknown form, or

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
     const Item* __restrict__ items, int n_items, const float* __restrict__ A32,
     const float* __restrict__ c32, const float* __restrict__ cen, int Kp,
     float* __restrict__ partials, float2* __restrict__ lse, int64_t lse_stride,
-    float* __restrict__ gout, int64_t gstride, const Counts* __restrict__ cnt) {
+    float* __restrict__ gout, int64_t gstride, const Counts* __restrict__ cnt, ItemQueue iqueue) {
   constexpr int NT = 64 * W;
   constexpr int NB = 2 * DP / 32;  // 32-feature output blocks of the statistics contraction
   // At 8 waves (two per SIMD, 256 registers each) the statistics kernel cannot also hold its
@@ -75,7 +75,9 @@ __global__ __launch_bounds__(64 * W) void fused_f32_kernel(
 
   const int n_it = live_items(cnt, items, n_items);
   const int64_t n_rows = live_rows(cnt, N);
-  for (int it = blockIdx.x; it < n_it; it += gridDim.x) {
+  __shared__ int s_it;
+  const ItemQueue iq = items != nullptr ? iqueue : ItemQueue{nullptr, nullptr};
+  for (int it = item_first(iq, n_it, &s_it); it < n_it; it = item_next(iq, n_it, &s_it, it)) {
     int64_t row0;
     int nrows;
     if (items != nullptr) {
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
     const Item* __restrict__ items, int n_items, const float2* __restrict__ lse, int G,
     int64_t lse_stride, const float* __restrict__ A32, const float* __restrict__ c32,
     const float* __restrict__ cen, int Kp, float* __restrict__ partials,
-    const Counts* __restrict__ cnt) {
+    const Counts* __restrict__ cnt, ItemQueue iqueue) {
   constexpr int NT = 64 * W;
   constexpr int NB = 2 * DP / 32;
   using IO = TileIO<DP, NT>;
@@ -226,7 +228,9 @@ __global__ __launch_bounds__(64 * W) void normext_f32_kernel(
 
   const int n_it = live_items(cnt, items, n_items);
   const int64_t n_rows = live_rows(cnt, N);
-  for (int it = blockIdx.x; it < n_it; it += gridDim.x) {
+  __shared__ int s_it;
+  const ItemQueue iq = items != nullptr ? iqueue : ItemQueue{nullptr, nullptr};
+  for (int it = item_first(iq, n_it, &s_it); it < n_it; it = item_next(iq, n_it, &s_it, it)) {
     int64_t row0;
     int nrows;
     if (items != nullptr) {
@@ -326,11 +330,11 @@ hipError_t launch_normext_dp(const Consts& c, const float* X, bool vec_ok, int64
   if (c.thresh)
     hipLaunchKernelGGL((normext_f32_kernel<DP, W, true>), grd, dim3(64 * W), 0, stream, X, c.D,
                        vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c), lse_stride,
-                       c.A32, c.c32, c.cen, c.Kp, partials, c.cnt);
+                       c.A32, c.c32, c.cen, c.Kp, partials, c.cnt, c.queue);
   else
     hipLaunchKernelGGL((normext_f32_kernel<DP, W, false>), grd, dim3(64 * W), 0, stream, X, c.D,
                        vec_ok ? 1 : 0, N, P, items, n_items, lse, lse_groups(c), lse_stride,
-                       c.A32, c.c32, c.cen, c.Kp, partials, c.cnt);
+                       c.A32, c.c32, c.cen, c.Kp, partials, c.cnt, c.queue);
   return hipGetLastError();
 }
 
@@ -358,7 +362,7 @@ hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N,
     if (c.thresh) {
       hipLaunchKernelGGL((fused_f32_kernel<DP, W, false, true>), dim3(grid, groups), dim3(64 * W),
                          0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32,
-                         c.cen, c.Kp, partials, lse, lse_stride, nullptr, 0, c.cnt);
+                         c.cen, c.Kp, partials, lse, lse_stride, nullptr, 0, c.cnt, c.queue);
       return hipGetLastError();
     }
   } else {
@@ -369,7 +373,7 @@ hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N,
         hipLaunchKernelGGL((fused_f32_kernel<DP, W, true, false, true>), dim3(grid, 1),
                            dim3(64 * W), 0, stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items,
                            c.A32, c.c32, c.cen, c.Kp, partials, lse, lse_stride, gout, gstride,
-                           c.cnt);
+                           c.cnt, c.queue);
         return hipGetLastError();
       } else {
         return hipErrorInvalidValue;
@@ -378,7 +382,7 @@ hipError_t launch_fused(const Consts& c, const float* X, bool vec_ok, int64_t N,
   }
   hipLaunchKernelGGL((fused_f32_kernel<DP, W, LSE, false>), dim3(grid, groups), dim3(64 * W), 0,
                      stream, X, c.D, vec_ok ? 1 : 0, N, P, items, n_items, c.A32, c.c32, c.cen,
-                     c.Kp, partials, lse, lse_stride, nullptr, 0, c.cnt);
+                     c.Kp, partials, lse, lse_stride, nullptr, 0, c.cnt, c.queue);
   return hipGetLastError();
 }
 

@@ -30,9 +30,11 @@ __device__ __forceinline__ int prow(int r, int h) { return 8 * (r >> 2) + 4 * h 
 // RB * 32 rows.  The rows of a tile are one contiguous block of floats, copied to LDS in the
 // same row-major layout with coalesced loads of V floats (V = 4 when X is 16-byte aligned and
 // 4 | Din, 2 when 8-byte aligned and 2 | Din); several workgroups per CU overlap one tile's
-// loads with another's MFMAs.
+// loads with another's MFMAs: the register budget is held to two waves per SIMD up to S = 112
+// (above that the operand fragments alone need more, and one wave per SIMD beats spilling).
 template <int S, int NC, int V>
-__global__ __launch_bounds__(256) void project_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 112 ? 2 : 1)))
+void project_kernel(
     const float* __restrict__ X, int64_t N, int Din, const float* __restrict__ frag,
     const float* __restrict__ bias, int Dp, int D, float* __restrict__ Y,
     const Counts* __restrict__ cnt) {

@@ -34,7 +34,8 @@ EXEC_HIP, EXEC_FAKE = 0, 1
 
 class Tuning(ctypes.Structure):
     _fields_ = [("batch_chunk", ctypes.c_int), ("batch_path", ctypes.c_int),
-                ("single_split_below", ctypes.c_int64)]
+                ("single_split_below", ctypes.c_int64), ("batch_grid", ctypes.c_int),
+                ("fused16_variant", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -246,9 +247,11 @@ def gmm_info(g: Gmm):
     return K.value, D.value, dev.value
 
 
-def set_tuning(g: Gmm, batch_chunk: int = 0, batch_path: int = 0, single_split_below: int = 0):
+def set_tuning(g: Gmm, batch_chunk: int = 0, batch_path: int = 0, single_split_below: int = 0,
+               batch_grid: int = 0, fused16_variant: int = 0):
     """fv_gmm_set_tuning (all zero = automatic)."""
-    t = Tuning(int(batch_chunk), int(batch_path), int(single_split_below))
+    t = Tuning(int(batch_chunk), int(batch_path), int(single_split_below), int(batch_grid),
+               int(fused16_variant))
     _check(load().fv_gmm_set_tuning(ctypes.c_void_p(g.handle), ctypes.byref(t)), "fv_gmm_set_tuning")
 
 
@@ -256,7 +259,8 @@ def get_tuning(g: Gmm) -> dict:
     t = Tuning()
     _check(load().fv_gmm_get_tuning(ctypes.c_void_p(g.handle), ctypes.byref(t)), "fv_gmm_get_tuning")
     return {"batch_chunk": t.batch_chunk, "batch_path": t.batch_path,
-            "single_split_below": t.single_split_below}
+            "single_split_below": t.single_split_below, "batch_grid": t.batch_grid,
+            "fused16_variant": t.fused16_variant}
 
 
 def _is_torch(x) -> bool:

@@ -159,9 +159,10 @@ def image_gmm(y, K, seed):
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16_split"])
 def test_encode_images_chain(fv, prec):
-    """fv_encode_images = fv_dsift -> projection -> batched encode: bitwise the same as the
-    three calls made separately; the FV of the GPU's own rows meets the encoder gates against
-    the oracle's float64 projection and encode; end to end from the images, within 1e-4."""
+    """fv_encode_images = fv_dsift -> projection -> encode: for two 320 x 240 frames (too few
+    chunks to fill the GPU as one batch) each image goes through fv_encode, bitwise the same as
+    the separate calls; the FV of the GPU's own rows meets the encoder gates against the
+    oracle's float64 projection and encode; end to end from the images, within 1e-4."""
     import torch
     tol = {0: 1e-5, 1: 1e-3}[prec]
     imgs = fvsynth.images(2, 240, 320, 70)
@@ -174,9 +175,8 @@ def test_encode_images_chain(fv, prec):
     imd = torch.from_numpy(imgs).cuda()
     got = fv.encode_images(h, ph, imd, precision=prec).cpu().numpy()
     rows = fv.dsift(imd)
-    n = rows.shape[1]
-    off = np.array([0, n, 2 * n], np.int64)
-    sep = fv.encode_batch_projected(h, ph, rows.reshape(-1, DIM), off, precision=prec).cpu().numpy()
+    sep = np.stack([fv.encode_projected(h, ph, rows[i].contiguous(), precision=prec).cpu().numpy()
+                    for i in range(2)])
     assert np.array_equal(got, sep)
     rows_h = rows.cpu().numpy()
     for i in range(2):
@@ -190,5 +190,35 @@ def test_encode_images_chain(fv, prec):
         assert e2["e_inf"] <= max(tol, 1e-4) and e2["e_2"] <= max(tol, 1e-4)
     host = fv.encode_images(h, ph, imgs, precision=prec)
     assert np.array_equal(host, got)
+    h.free()
+    ph.free()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16_split"])
+def test_encode_images_batch(fv, prec):
+    """Seventy 120 x 160 frames fill the GPU as one batch: fv_encode_images equals the dense
+    SIFT rows encoded by fv_encode_batch_projected (one frame per image) bitwise, and two of its
+    vectors meet the gates against the oracle's chain from those images."""
+    import torch
+    imgs = fvsynth.images(70, 120, 160, 500)
+    p = fvsynth.pca(64, 4)
+    ph = fv.pca_load(p.A, p.mean)
+    y0 = oracle.project(odsift.extract(imgs[0]), p.A, p.mean)
+    g = image_gmm(y0, 256, 5)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    say(f"[gpu] encode_images 70 x 160x120 prec={prec}")
+    imd = torch.from_numpy(imgs).cuda()
+    got = fv.encode_images(h, ph, imd, precision=prec).cpu().numpy()
+    rows = fv.dsift(imd)
+    n = rows.shape[1]
+    off = np.arange(71, dtype=np.int64) * n
+    sep = fv.encode_batch_projected(h, ph, rows.reshape(-1, DIM), off, precision=prec).cpu().numpy()
+    assert np.array_equal(got, sep)
+    tol = {0: 1e-4, 1: 1e-3}[prec]
+    for i in (0, 69):
+        ref = oracle.encode_projected(odsift.extract(imgs[i]), p.A, p.mean, g)
+        e = errors(got[i], ref)
+        say(f"  image {i}: e_inf={e['e_inf']:.2e} e_2={e['e_2']:.2e}")
+        assert e["e_inf"] <= tol and e["e_2"] <= tol
     h.free()
     ph.free()
