@@ -163,8 +163,10 @@ int fv_encode_batch(const fv_gmm* gmm, const float* X, const int64_t* offsets, i
  *                       the first pass; 0 = automatic: the resident workgroup count); the
  *                       kernels loop over the work items, so results do not depend on it
  *   fused16_variant     fused 16-bit kernel at 256 components, DP <= 64: 0 = automatic (the
- *                       wave-specialised kernel), 1 = wave-specialised, 2 = single-role
- *                       (transposed E-step); results agree within rounding
+ *                       pipelined kernel), 1 = wave-specialised with two barriers per tile,
+ *                       2 = single-role (transposed E-step), 3 = wave-specialised and
+ *                       pipelined (one barrier per tile); 1 and 3 give the same bits, 2 agrees
+ *                       within rounding
  * Not synchronised with encodes running concurrently on the same handle.  Errors: FV_E_INVAL.
  */
 typedef struct fv_tuning {
@@ -187,8 +189,8 @@ int fv_gmm_get_tuning(const fv_gmm* gmm, fv_tuning* tuning);
  *   FV_SPLIT_GAMMA=0      FP32 two-pass frames recompute the E-step in the second pass instead
  *                         of reading the posterior factors the first pass wrote
  *   FV_MAX_GRID=n         cap the first grid dimension of every statistics launch at n
- *   FV_FUSED16=t          the single-role fused 16-bit kernel instead of the wave-specialised
- *                         one
+ *   FV_FUSED16=w|t|p      the fused 16-bit kernel variant at 256 components: wave-specialised,
+ *                         single-role or pipelined (fused16_variant 1, 2, 3), over the tuning
  */
 
 /*

@@ -19,7 +19,7 @@ from . import fv as _fv
 CHUNKS = (256, 512, 1024, 2048, 4096)
 PATHS = (1, 2)  # fused single pass, two-pass
 GRIDS = (0.5, 2.0)  # statistics grid as a multiple of the resident workgroups (1 = automatic)
-VARIANTS = (1, 2)  # fused 16-bit kernel: wave-specialised, single-role
+VARIANTS = (3, 1, 2)  # fused 16-bit kernel: pipelined, wave-specialised, single-role
 
 
 def cache_path() -> str:

@@ -358,10 +358,11 @@ int grid_cap(int g) {
   return x >= 1 ? std::min(g, x) : g;
 }
 
-// FV_FUSED16=t (measurements): the single-role fused 16-bit kernel.
-bool fused16_env_single() {
+// FV_FUSED16 (measurements): w, t or p forces the 16-bit fused kernel variant 1, 2 or 3.
+int fused16_env() {
   const char* e = std::getenv("FV_FUSED16");
-  return e && e[0] == 't';
+  if (!e) return 0;
+  return e[0] == 'w' ? 1 : e[0] == 't' ? 2 : e[0] == 'p' ? 3 : 0;
 }
 
 // Path override for tests and measurements: FV_PATH=fused|split (default: automatic).
@@ -895,7 +896,7 @@ int fv_gmm_set_tuning(fv_gmm* gmm, const fv_tuning* t) {
   }
   if (t->batch_chunk < 0 || (t->batch_chunk > 0 && t->batch_chunk < 128) || t->batch_path < 0 ||
       t->batch_path > 2 || t->single_split_below < 0 || t->batch_grid < 0 ||
-      t->batch_grid > (1 << 20) || t->fused16_variant < 0 || t->fused16_variant > 2)
+      t->batch_grid > (1 << 20) || t->fused16_variant < 0 || t->fused16_variant > 3)
     return FV_E_INVAL;
   gmm->batch_chunk = t->batch_chunk;
   gmm->batch_path = t->batch_path;
@@ -1094,7 +1095,7 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
   key.pca = pca ? pca->serial : 0;
   key.cap = grid_cap(1 << 30) == (1 << 30) ? 0 : grid_cap(1 << 30);
   key.grid = gmm->batch_grid;
-  key.variant = gmm->fused16_variant + (fused16_env_single() ? 4 : 0);
+  key.variant = gmm->fused16_variant + 4 * fused16_env();
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   if (!(flags & FV_OUT_DEVICE))
@@ -1279,7 +1280,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   key.pca = pca ? pca->serial : 0;
   key.cap = grid_cap(1 << 30) == (1 << 30) ? 0 : grid_cap(1 << 30);
   key.grid = gmm->batch_grid;
-  key.variant = gmm->fused16_variant + (fused16_env_single() ? 4 : 0);
+  key.variant = gmm->fused16_variant + 4 * fused16_env();
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
   FV_HIP(hipEventRecord(ws->pin_done, s));

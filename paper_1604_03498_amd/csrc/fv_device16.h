@@ -51,11 +51,46 @@ __device__ __forceinline__ uint16_t bits16(T v) {
   return __builtin_bit_cast(uint16_t, v);
 }
 
-// hi/lo split of an FP32 value (round to nearest even in both conversions).
+// hi/lo split of an FP32 value (round to nearest even in both conversions).  The difference
+// v - hi is exact and must be formed from the rounded v: the empty asm keeps instruction
+// selection from fusing it with a product that produced v (a mixed-precision FMA would form
+// lo from the unrounded product).
 template <class T>
 __device__ __forceinline__ void split16(float v, T& hi, T& lo) {
+  asm volatile("" : "+v"(v));
   hi = (T)v;
   lo = (T)(v - (float)hi);
+}
+
+// hi/lo split of two FP32 values at once, with the same results as split16 on each: one
+// packed conversion gives both hi, each is widened back exactly, one packed conversion gives
+// both lo.  hi and lo hold the pair as two 16-bit halves (v0 in the low half).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <class T>
+struct Pack16;
+template <>
+struct Pack16<__bf16> {
+  typedef __bf16 v2 __attribute__((ext_vector_type(2)));
+  __device__ __forceinline__ static float widen_lo(uint32_t p) { return __uint_as_float(p << 16); }
+  __device__ __forceinline__ static float widen_hi(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+};
+template <>
+struct Pack16<_Float16> {
+  typedef _Float16 v2 __attribute__((ext_vector_type(2)));
+  __device__ __forceinline__ static float widen_lo(uint32_t p) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(p & 0xffffu));
+  }
+  __device__ __forceinline__ static float widen_hi(uint32_t p) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(p >> 16));
+  }
+};
+template <class T>
+__device__ __forceinline__ void split16x2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
+  using P = Pack16<T>;
+  asm volatile("" : "+v"(v0), "+v"(v1));  // as in split16: the rounded values are split
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){v0, v1}, typename P::v2));
+  const float d0 = v0 - P::widen_lo(hi), d1 = v1 - P::widen_hi(hi);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){d0, d1}, typename P::v2));
 }
 
 __device__ __forceinline__ constexpr int tpos(int row) {
@@ -240,6 +275,105 @@ struct TileIO16Rows {
     }
   }
 };
+
+// Row-major 16-bit tile without a transposed copy (pipelined fused kernel): kTile rows of
+// 2*DP <= 128 features (x - centre, then its square), hi and lo arrays.  Rows are 80 dwords
+// apart (16 banks modulo 64), and the 16-byte chunk c of row r is stored at chunk
+// c ^ ((r >> 2) & 3).  Then 16 consecutive rows of one chunk (the E-step's 16-byte reads) and
+// 4 consecutive rows of 4 aligned chunks (the statistics' transposed 8-byte reads) each fall
+// on distinct banks.
+template <int DP>
+struct TileR16 {
+  static_assert(DP <= 64, "two 64-feature halves at most");
+  static constexpr int RS = 160;           // elements per row
+  static constexpr int kArr = kTile * RS;  // elements per array
+  __device__ __forceinline__ static int at(int row, int chunk) {
+    return row * RS + (chunk ^ ((row >> 2) & 3)) * 8;
+  }
+};
+
+// Converts the fetched rows (TileIO16Rows::fetch, NT threads) into a TileR16: x - centre and
+// its square, each split into hi/lo, 8-byte stores.
+template <int DP, int NT>
+struct TileStoreR16 {
+  using TR = TileR16<DP>;
+  using IO = TileIO16Rows<DP, NT>;
+  template <class T, bool SPLIT>
+  __device__ __forceinline__ static void store(uint16_t* hi_arr, uint16_t* lo_arr,
+                                               const f32x4 (&pre)[IO::kPer], const float* cen,
+                                               int tid) {
+#pragma unroll
+    for (int q = 0; q < IO::kPer; ++q) {
+      const int idx = tid + q * NT;
+      if (IO::kSlots % NT != 0 && idx >= IO::kSlots) continue;
+      const int row = idx % kTile;
+      const int c4 = (idx / kTile) * 4;
+      const f32x4 xc = pre[q] - *reinterpret_cast<const f32x4*>(cen + c4);
+#pragma unroll
+      for (int sq = 0; sq < 2; ++sq) {
+        const int f0 = c4 + sq * DP;
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = sq ? xc[e] * xc[e] : xc[e];
+        uint32_t h0, h1, l0, l1;
+        split16x2<T>(v[0], v[1], h0, l0);
+        split16x2<T>(v[2], v[3], h1, l1);
+        const int off = TR::at(row, f0 >> 3) + (f0 & 7);
+        *reinterpret_cast<u32x2*>(hi_arr + off) = u32x2{h0, h1};
+        if (SPLIT) *reinterpret_cast<u32x2*>(lo_arr + off) = u32x2{l0, l1};
+      }
+    }
+  }
+};
+
+// gfx950 transposed LDS read of 16-bit data (ds_read_b64_tr_b16): within each group of 16
+// lanes, lane 4b + c receives element c of the 8-byte chunks addressed by lanes b, b + 4,
+// b + 8 and b + 12 of the group, as its values 0..3.
+typedef short s16x4 __attribute__((vector_size(8)));
+__device__ __forceinline__ s16x4 lds_read_tr16(const uint16_t* p) {
+  return __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) s16x4*)(p));
+}
+
+// The statistics' A operand (features x rows) of feature block b and 16-row step q from a
+// TileR16 array, in the row order of the posterior operand: lane (j, h) gets feature 32 b + j
+// at rows 16 q + 4 h + e and 16 q + 8 + 4 h + e (e = 0..3).  Each lane addresses row
+// 16 q + 4 h + (i >> 2) (and + 8), features 32 b + 16 (j >> 4) + 4 (i & 3) .. + 3
+// (i = lane & 15); both rows' chunk swizzle is fixed by h, so the offsets are affine in q, b.
+struct TrOffsets {
+  int o1, o2;  // element offsets of the two reads for q = b = 0
+  __device__ __forceinline__ TrOffsets(int lane) {
+    const int i = lane & 15, j = lane & 31, h = lane >> 5;
+    const int cp = 2 * (j >> 4) + ((i & 3) >> 1);  // chunk within the block's four
+    const int row = 4 * h + (i >> 2);
+    o1 = row * 160 + (cp ^ h) * 8 + 4 * (i & 1);
+    o2 = (row + 8) * 160 + (cp ^ h ^ 2) * 8 + 4 * (i & 1);
+  }
+};
+
+// Per interval: the two read bases of one array as LDS pointers.  The empty asm keeps the
+// compiler from hoisting every (q, b) address out of the loop (32 registers held across the
+// kernel); each read then costs one add of a constant.
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+struct TrBase {
+  lds_s16x4* p1;
+  lds_s16x4* p2;
+  __device__ __forceinline__ TrBase(const uint16_t* arr, const TrOffsets& o) {
+    int o1 = o.o1, o2 = o.o2;
+    asm volatile("" : "+v"(o1), "+v"(o2));
+    p1 = (lds_s16x4*)(arr + o1);
+    p2 = (lds_s16x4*)(arr + o2);
+  }
+};
+
+template <class V>
+__device__ __forceinline__ V tr_operand(const TrBase& t, int q, int b) {
+  const int d = (16 * q * 160 + 32 * b) / 4;  // in 8-byte units
+  const s16x4 r1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(t.p1 + d);
+  const s16x4 r2 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(t.p2 + d);
+  const s16x4 both[2] = {r1, r2};
+  return __builtin_bit_cast(V, both);
+}
 
 // E-step, 16-bit operands.  bh/bl: per k-step s (16 features), the lane's 8 constants
 // A[16s + 8h + e][comp] as hi/lo fragments.  With COMP, chains of two k-steps (32 features)
