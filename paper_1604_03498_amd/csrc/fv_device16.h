@@ -51,13 +51,12 @@ __device__ __forceinline__ uint16_t bits16(T v) {
   return __builtin_bit_cast(uint16_t, v);
 }
 
-// hi/lo split of an FP32 value (round to nearest even in both conversions).  The difference
-// v - hi is exact and must be formed from the rounded v: the empty asm keeps instruction
-// selection from fusing it with a product that produced v (a mixed-precision FMA would form
-// lo from the unrounded product).
+// hi/lo split of an FP32 value (round to nearest even in both conversions).  Where v comes
+// from a product, instruction selection may fuse the product into v - hi (a mixed-precision
+// FMA forms lo from the unrounded product, slightly more accurate); callers that must give
+// the same bits as another kernel make v opaque first (an empty asm on it).
 template <class T>
 __device__ __forceinline__ void split16(float v, T& hi, T& lo) {
-  asm volatile("" : "+v"(v));
   hi = (T)v;
   lo = (T)(v - (float)hi);
 }
@@ -84,10 +83,11 @@ struct Pack16<_Float16> {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(p >> 16));
   }
 };
+// The caller makes v0 and v1 opaque where they come from a product (as split16 does for its
+// input), so that their rounded values are split.
 template <class T>
 __device__ __forceinline__ void split16x2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
   using P = Pack16<T>;
-  asm volatile("" : "+v"(v0), "+v"(v1));  // as in split16: the rounded values are split
   hi = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){v0, v1}, typename P::v2));
   const float d0 = v0 - P::widen_lo(hi), d1 = v1 - P::widen_hi(hi);
   lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){d0, d1}, typename P::v2));
@@ -254,7 +254,8 @@ struct TileIO16Rows {
         uint16_t hi[4], lo[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float v = sq ? xc[e] * xc[e] : xc[e];
+          float v = sq ? xc[e] * xc[e] : xc[e];
+          asm volatile("" : "+v"(v));  // the rounded square, as TileStoreR16 splits it
           T hh, ll;
           split16<T>(v, hh, ll);
           hi[e] = bits16<T>(hh);
@@ -277,18 +278,21 @@ struct TileIO16Rows {
 };
 
 // Row-major 16-bit tile without a transposed copy (pipelined fused kernel): kTile rows of
-// 2*DP <= 128 features (x - centre, then its square), hi and lo arrays.  Rows are 80 dwords
-// apart (16 banks modulo 64), and the 16-byte chunk c of row r is stored at chunk
-// c ^ ((r >> 2) & 3).  Then 16 consecutive rows of one chunk (the E-step's 16-byte reads) and
-// 4 consecutive rows of 4 aligned chunks (the statistics' transposed 8-byte reads) each fall
-// on distinct banks.
+// 2*DP <= 128 features (x - centre, then its square), hi and lo arrays.  Rows are kRowDw = 80
+// dwords apart and the 16-byte chunk c of row r is stored at chunk c ^ ((r >> 2) & kSwz), so
+// that 16 consecutive rows of one chunk (the E-step's 16-byte reads) and 4 rows of 4 aligned
+// chunks (the statistics' transposed 8-byte reads) each fall on distinct banks of 64.  (A
+// layout for 32 banks, 72 dwords and swizzle mask 1, measured 3.9 times the bank-conflict
+// cycles.)
+constexpr int kRowDw = 80;
+constexpr int kSwz = 3;
 template <int DP>
 struct TileR16 {
   static_assert(DP <= 64, "two 64-feature halves at most");
-  static constexpr int RS = 160;           // elements per row
+  static constexpr int RS = 2 * kRowDw;    // elements per row
   static constexpr int kArr = kTile * RS;  // elements per array
   __device__ __forceinline__ static int at(int row, int chunk) {
-    return row * RS + (chunk ^ ((row >> 2) & 3)) * 8;
+    return row * RS + (chunk ^ ((row >> 2) & kSwz)) * 8;
   }
 };
 
@@ -314,7 +318,10 @@ struct TileStoreR16 {
         const int f0 = c4 + sq * DP;
         float v[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = sq ? xc[e] * xc[e] : xc[e];
+        for (int e = 0; e < 4; ++e) {
+          v[e] = sq ? xc[e] * xc[e] : xc[e];
+          asm volatile("" : "+v"(v[e]));  // split the rounded square (split16x2)
+        }
         uint32_t h0, h1, l0, l1;
         split16x2<T>(v[0], v[1], h0, l0);
         split16x2<T>(v[2], v[3], h1, l1);
@@ -346,8 +353,8 @@ struct TrOffsets {
     const int i = lane & 15, j = lane & 31, h = lane >> 5;
     const int cp = 2 * (j >> 4) + ((i & 3) >> 1);  // chunk within the block's four
     const int row = 4 * h + (i >> 2);
-    o1 = row * 160 + (cp ^ h) * 8 + 4 * (i & 1);
-    o2 = (row + 8) * 160 + (cp ^ h ^ 2) * 8 + 4 * (i & 1);
+    o1 = row * 2 * kRowDw + (cp ^ (h & kSwz)) * 8 + 4 * (i & 1);
+    o2 = (row + 8) * 2 * kRowDw + (cp ^ ((h + 2) & kSwz)) * 8 + 4 * (i & 1);
   }
 };
 
@@ -368,7 +375,7 @@ struct TrBase {
 
 template <class V>
 __device__ __forceinline__ V tr_operand(const TrBase& t, int q, int b) {
-  const int d = (16 * q * 160 + 32 * b) / 4;  // in 8-byte units
+  const int d = (16 * q * 2 * kRowDw + 32 * b) / 4;  // in 8-byte units
   const s16x4 r1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(t.p1 + d);
   const s16x4 r2 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(t.p2 + d);
   const s16x4 both[2] = {r1, r2};
