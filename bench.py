@@ -49,9 +49,9 @@ STATS_KERNELS = {
     ("fp32", "split"): ["fused_f32_kernel<64, 8, true, false, true>", "sliced_f32_kernel<64, 8, false, true>"],
     ("fp32", "fused"): ["fused_f32_kernel<64, 8, false, false, false>"],
     ("bf16_split", "split"): ["lse16_kernel<64, 8>", "sliced16_kernel<64, false>"],
-    ("bf16_split", "fused"): ["fused16t_kernel<64, 8, false>"],
+    ("bf16_split", "fused"): ["fused16p_kernel<64, false>"],
     ("fp16_split", "split"): ["lse16_kernel<64, 8>", "sliced16_kernel<64, false>"],
-    ("fp16_split", "fused"): ["fused16t_kernel<64, 8, false>"],
+    ("fp16_split", "fused"): ["fused16p_kernel<64, false>"],
 }
 
 
