@@ -211,8 +211,9 @@ int fv_kernel_timing_read(int which, double* total_ms, int64_t* launches);
  * values are reduced to m dimensions by PCA and the normalised image coordinates appended,
  * giving the D = m + 2 the GMM is trained on).  The prologue computes, per descriptor,
  *   y = A (x - m),   A [D x Din] row-major, m [Din]
- * so appended coordinates are identity rows of A (with m = 0 in their columns).  One FP32
- * MFMA contraction per 32-descriptor tile; y is FP32 in every precision form.
+ * so appended coordinates are identity rows of A (with m = 0 in their columns).  One MFMA
+ * contraction per 32-descriptor tile: FP32 MFMA for the FP32 encoder form, the bf16 hi/lo
+ * split (three products, FP32 accumulation) for the 16-bit forms; y is FP32 in every form.
  *
  * fv_pca_load copies A and m (host pointers) to `device` and precomputes -A m in FP64.
  * Requires 1 <= Din <= 256 (FV_E_UNSUPPORTED above), 1 <= D <= the fv_limits maximum, and
@@ -226,9 +227,11 @@ int fv_pca_info(const fv_pca* pca, int* Din, int* D, int* device);
 
 /*
  * Projection alone: X [N x Din] -> Y [N x D], both row-major float32; FV_X_DEVICE and
- * FV_OUT_DEVICE say where X and Y live, FV_ASYNC as for fv_encode.  Errors: FV_E_INVAL
- * (null pointers, N < 0, other flags), FV_E_NOMEM, FV_E_DEVICE.
+ * FV_OUT_DEVICE say where X and Y live, FV_ASYNC as for fv_encode; FV_PROJ_SPLIT16 selects
+ * the split-bf16 contraction the 16-bit encoder forms use (the same bits as their prologue).
+ * Errors: FV_E_INVAL (null pointers, N < 0, other flags), FV_E_NOMEM, FV_E_DEVICE.
  */
+#define FV_PROJ_SPLIT16 64u
 int fv_project(const fv_pca* pca, const float* X, int64_t N, float* Y, unsigned flags,
                void* hip_stream);
 

@@ -9,7 +9,7 @@ from .fv import (  # noqa: F401
     strerror, last_device_error, kernel_timing, kernel_timing_read,
     OK, PENDING, E_INVAL, E_NOMEM, E_DEVICE, E_BUDGET, E_AGAIN, E_NOTFOUND, E_TIMEOUT,
     E_UNSUPPORTED, PREC_FP32, PREC_BF16_SPLIT, PREC_FP16_SPLIT, PREC_BF16, X_DEVICE, OUT_DEVICE,
-    NO_POWER_NORM, NO_L2_NORM, ASYNC, THRESHOLD, THRESHOLD_TAU, EXPORTED_SYMBOLS, EXEC_HIP,
+    NO_POWER_NORM, NO_L2_NORM, ASYNC, THRESHOLD, THRESHOLD_TAU, PROJ_SPLIT16, EXPORTED_SYMBOLS, EXEC_HIP,
     EXEC_FAKE, Server, ServerConfig,
     server_config, set_tuning, get_tuning, Tuning, Pca, pca_load, project, encode_projected,
     encode_batch_projected, em_step, em_fit, stream_release, DSIFT_DIM, dsift_rows, dsift,

@@ -1044,7 +1044,8 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
   auto enqueue = [&]() -> int {
     if (pca && N > 0) {
       hipEvent_t tp = ext ? nullptr : timing_begin(s);
-      FV_HIP(fv::launch_project(pca->p, Xd, N, ydev, project_grid(gmm->device, N), s));
+      FV_HIP(fv::launch_project(pca->p, Xd, N, ydev, project_grid(gmm->device, N), s, nullptr,
+                                precision != FV_PREC_FP32));
       timing_end(tp, 2, s);
     }
     if (n_items > 0) {
@@ -1230,7 +1231,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
     if (pca) {
       hipEvent_t tp = timing_begin(s);
       FV_HIP(fv::launch_project(pca->p, Xd, cp.rows, ydev, project_grid(gmm->device, cp.rows),
-                                s, dcounts));
+                                s, dcounts, precision != FV_PREC_FP32));
       timing_end(tp, 2, s);
     }
     hipEvent_t t0 = timing_begin(s);
@@ -1412,7 +1413,24 @@ int fv_pca_load(int Din, int D, const float* A, const float* mean, int device, f
     }
     bias[c] = (float)(-am);
   }
-  const size_t oF = 0, oB = align256(frag.size() * 4), total = oB + align256(bias.size() * 4);
+  // the split form's bf16 hi/lo fragments: element e of (step s, half h, column c) is
+  // A[c][16 s + 8 h + e]; hi = rne(a), lo = rne(a - hi) (a - hi exact in FP32)
+  const int ns16 = (Din + 63) / 64 * 4;
+  std::vector<uint16_t> fhi((size_t)ns16 * 2 * p.Dp * 8, 0), flo(fhi.size(), 0);
+  for (int st = 0; st < ns16; ++st)
+    for (int hh = 0; hh < 2; ++hh)
+      for (int c = 0; c < D; ++c)
+        for (int e = 0; e < 8; ++e) {
+          const int k = 16 * st + 8 * hh + e;
+          if (k >= Din) continue;
+          const float a = A[(size_t)c * Din + k];
+          const uint16_t hi = bf16_rne(a);
+          const size_t o = (((size_t)st * 2 + hh) * p.Dp + c) * 8 + e;
+          fhi[o] = hi;
+          flo[o] = bf16_rne(a - bf16_to_f32(hi));
+        }
+  const size_t oF = 0, oB = align256(frag.size() * 4), oH = oB + align256(bias.size() * 4),
+               oL = oH + align256(fhi.size() * 2), total = oL + align256(flo.size() * 2);
   DeviceGuard g(device);
   if (g.status() != hipSuccess) return hip_fail(g.status());
   std::unique_ptr<fv_pca> h(new (std::nothrow) fv_pca());
@@ -1421,12 +1439,16 @@ int fv_pca_load(int Din, int D, const float* A, const float* mean, int device, f
   FV_HIP(hipMalloc(&blk, total));
   hipError_t e = hipMemcpy(blk + oF, frag.data(), frag.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(blk + oB, bias.data(), bias.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(blk + oH, fhi.data(), fhi.size() * 2, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(blk + oL, flo.data(), flo.size() * 2, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(blk);
     return hip_fail(e);
   }
   p.frag = reinterpret_cast<const float*>(blk + oF);
   p.bias = reinterpret_cast<const float*>(blk + oB);
+  p.f16hi = reinterpret_cast<const uint16_t*>(blk + oH);
+  p.f16lo = reinterpret_cast<const uint16_t*>(blk + oL);
   h->Din = Din;
   h->D = D;
   h->device = device;
@@ -1462,7 +1484,7 @@ int fv_pca_info(const fv_pca* pca, int* Din, int* D, int* device) {
 int fv_project(const fv_pca* pca, const float* X, int64_t N, float* Y, unsigned flags,
                void* hip_stream) {
   if (!pca || N < 0 || (N > 0 && (!X || !Y))) return FV_E_INVAL;
-  if (flags & ~(FV_X_DEVICE | FV_OUT_DEVICE | FV_ASYNC)) return FV_E_INVAL;
+  if (flags & ~(FV_X_DEVICE | FV_OUT_DEVICE | FV_ASYNC | FV_PROJ_SPLIT16)) return FV_E_INVAL;
   if (N > ((int64_t)1 << 40) / std::max(pca->Din, pca->D)) return FV_E_UNSUPPORTED;
   if (N == 0) return FV_OK;
   DeviceGuard g(pca->device);
@@ -1485,7 +1507,8 @@ int fv_project(const fv_pca* pca, const float* X, int64_t N, float* Y, unsigned 
   float* Yd = (flags & FV_OUT_DEVICE) ? Y : reinterpret_cast<float*>(ws->dev + b_x);
   if ((reinterpret_cast<uintptr_t>(Yd) & 3) != 0) return FV_E_INVAL;
   hipEvent_t tp = timing_begin(s);
-  FV_HIP(fv::launch_project(pca->p, Xd, N, Yd, project_grid(pca->device, N), s));
+  FV_HIP(fv::launch_project(pca->p, Xd, N, Yd, project_grid(pca->device, N), s, nullptr,
+                            (flags & FV_PROJ_SPLIT16) != 0));
   timing_end(tp, 2, s);
   if (!(flags & FV_OUT_DEVICE))
     FV_HIP(hipMemcpyAsync(Y, Yd, (size_t)N * pca->D * 4, hipMemcpyDeviceToHost, s));

@@ -278,11 +278,17 @@ struct ProjConsts {
   int Dp;  // D rounded up to a multiple of 32
   const float* frag;  // [2S][Dp], frag[k][c] = A[c][k] (zero for k >= Din or c >= D)
   const float* bias;  // [Dp], -(A m)[c] computed in double (zero for c >= D)
+  // bf16 hi/lo fragments of A for the split form, [NS16][2][Dp][8] (NS16 = 16 rounded-up
+  // steps of 16 input features, 4 | NS16): element e of (step s, half h, column c) is
+  // A[c][16 s + 8 h + e] (zero past Din or D)
+  const uint16_t* f16hi;
+  const uint16_t* f16lo;
 };
 // With cnt (a batched sequence) the row count is read from cnt->rows; N is then only the
-// capacity the grid was sized for.
+// capacity the grid was sized for.  split16: the split-bf16 contraction (16-bit encoder forms)
+// instead of FP32.
 hipError_t launch_project(const ProjConsts& p, const float* X, int64_t N, float* Y, int grid,
-                          hipStream_t stream, const Counts* cnt = nullptr);
+                          hipStream_t stream, const Counts* cnt = nullptr, bool split16 = false);
 
 // EM step (fv_em.hip): M-step from the statistics partials, log-likelihood from the first
 // pass's row normalisers (ll_part: em_loglik_blocks(N) workgroup sums, log2 units).

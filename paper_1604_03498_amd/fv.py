@@ -16,6 +16,7 @@ E_INVAL, E_NOMEM, E_DEVICE, E_BUDGET = -1, -2, -3, -4
 E_AGAIN, E_NOTFOUND, E_TIMEOUT, E_UNSUPPORTED = -5, -6, -7, -8
 PREC_FP32, PREC_BF16_SPLIT, PREC_FP16_SPLIT, PREC_BF16 = 0, 1, 2, 3
 X_DEVICE, OUT_DEVICE, NO_POWER_NORM, NO_L2_NORM, ASYNC, THRESHOLD = 1, 2, 4, 8, 16, 32
+PROJ_SPLIT16 = 64  # fv_project: the split-bf16 contraction of the 16-bit encoder forms
 THRESHOLD_TAU = 1e-6  # posteriors at or below it are left out under THRESHOLD
 DSIFT_DIM = 130  # dense-SIFT row: 128 values + the centre's normalised x and y
 
@@ -413,9 +414,9 @@ def pca_load(A, mean, device: int = 0) -> Pca:
     return Pca(h.value, Din, D, int(device))
 
 
-def project(p: Pca, X, out=None, stream=None):
+def project(p: Pca, X, out=None, stream=None, split16: bool = False):
     """fv_project: [N, Din] -> [N, D] (device tensors in, device tensor out; host arrays in,
-    host array out)."""
+    host array out).  split16: the split-bf16 contraction (as inside the 16-bit forms)."""
     xp, n, xdev, _keep = _marshal_x(p, X, p.Din)
     shape = (n, p.D)
     if out is None:
@@ -434,7 +435,7 @@ def project(p: Pca, X, out=None, stream=None):
         if out.dtype != np.float32 or out.shape != shape or not out.flags.c_contiguous:
             raise ValueError(f"out must be a contiguous float32 array of shape {shape}")
         op, odev = out.ctypes.data, False
-    f = (X_DEVICE if xdev else 0) | (OUT_DEVICE if odev else 0)
+    f = (X_DEVICE if xdev else 0) | (OUT_DEVICE if odev else 0) | (PROJ_SPLIT16 if split16 else 0)
     s = _stream_handle(stream, p.device) if (xdev or odev or stream is not None) else 0
     _check(load().fv_project(ctypes.c_void_p(p.handle), ctypes.c_void_p(xp), int(n),
                              ctypes.c_void_p(op), f, ctypes.c_void_p(s)), "fv_project")

@@ -5,6 +5,10 @@ The projection alone is checked entrywise against a rigorous float32 dot-product
 u = 2^-24 and n = Din + 2 roundings per output (Din products accumulated onto the rounded
 bias -A m),
     |y_gpu - y| <= n u (|A m| + sum_k |A_ck| |x_tk|) / (1 - n u) + u |A m|.
+The split-bf16 projection of the 16-bit forms (fv_project with PROJ_SPLIT16) forms every
+product a x as ah xh + al xh + ah xl with ah = rne(a), al = rne(a - ah) (and likewise for x): the
+dropped al xl and the two lo roundings leave at most 3 * 2^-18 (1 + 2^-8) |a| |x| per product,
+which adds 2^-16 sum_k |A_ck| |x_tk| to the float32 bound above (taken with n = 3 Din + 2).
 The encodings use the usual gates: E_inf, E_2 <= 1e-5 (FP32), 1e-3 (split forms).
 Inputs: a stand-in PCA (orthonormal 128 -> 62 block plus two pass-through coordinates, Din =
 130, D = 64) and raw descriptors built so that their projection is a GMM sample.
@@ -37,12 +41,14 @@ def fv():
     return fvmod
 
 
-def projection_bound(X, A, m):
+def projection_bound(X, A, m, split16=False):
     A64 = A.astype(np.float64)
     am = np.abs(A64 @ m.astype(np.float64))
-    n = X.shape[1] + 2
-    s = np.abs(X.astype(np.float64)) @ np.abs(A64).T + am[None, :]
-    return n * U * s / (1 - n * U) + U * am[None, :]
+    n = (3 if split16 else 1) * X.shape[1] + 2
+    ax = np.abs(X.astype(np.float64)) @ np.abs(A64).T
+    s = ax + am[None, :]
+    b = n * U * s / (1 - n * U) + U * am[None, :]
+    return b + (2.0 ** -16) * ax if split16 else b
 
 
 @pytest.mark.parametrize("Din,D,N", [(130, 64, 5000), (128, 64, 777), (130, 82, 3001),
@@ -63,6 +69,13 @@ def test_project_matches_float64(fv, Din, D, N):
     assert np.all(err <= bound)
     # host pointers give the same bits; an unaligned device row start (Din odd) is accepted
     assert np.array_equal(fv.project(p, X), got)
+    # the split-bf16 contraction of the 16-bit forms, against its own bound
+    got16 = fv.project(p, torch.from_numpy(X).cuda(), split16=True).cpu().numpy()
+    err16 = np.abs(got16.astype(np.float64) - ref)
+    bound16 = projection_bound(X, A, m, split16=True)
+    say(f"  split16: max|err|={err16.max():.3e}  max err/bound={np.max(err16 / bound16):.3f}")
+    assert np.all(err16 <= bound16)
+    assert np.array_equal(fv.project(p, X, split16=True), got16)
 
 
 CASES = [
@@ -92,9 +105,9 @@ def test_encode_projected_matches_oracle(fv, case, prec):
     assert np.all(np.isfinite(got))
     assert e["e_inf"] <= tol and e["e_2"] <= tol, e
     # host input gives the same bits; the projection + encode equals encode of fv_project's
-    # output (the same kernels in the same order)
+    # output (the same kernels in the same order; the 16-bit forms project with the split)
     assert np.array_equal(fv.encode_projected(h, hp, X, precision=prec), got)
-    Y = fv.project(hp, torch.from_numpy(X).cuda())
+    Y = fv.project(hp, torch.from_numpy(X).cuda(), split16=prec != 0)
     assert np.array_equal(fv.encode(h, Y, precision=prec).cpu().numpy(), got)
 
 
