@@ -284,23 +284,26 @@ struct TileIO16Rows {
 // chunks (the statistics' transposed 8-byte reads) each fall on distinct banks of 64.  (A
 // layout for 32 banks, 72 dwords and swizzle mask 1, measured 3.9 times the bank-conflict
 // cycles.)
+// A second layout, 72 dwords with mask 1 (18 KB per hi/lo pair instead of 20), lets eight
+// wave-private tiles fit in LDS at the cost of 2-way conflicts on those reads.
 constexpr int kRowDw = 80;
 constexpr int kSwz = 3;
-template <int DP>
+template <int DP, int RDW = kRowDw, int SWZ = kSwz>
 struct TileR16 {
   static_assert(DP <= 64, "two 64-feature halves at most");
-  static constexpr int RS = 2 * kRowDw;    // elements per row
+  static constexpr int RS = 2 * RDW;       // elements per row
   static constexpr int kArr = kTile * RS;  // elements per array
+  static constexpr int kSw = SWZ;
   __device__ __forceinline__ static int at(int row, int chunk) {
-    return row * RS + (chunk ^ ((row >> 2) & kSwz)) * 8;
+    return row * RS + (chunk ^ ((row >> 2) & SWZ)) * 8;
   }
 };
 
 // Converts the fetched rows (TileIO16Rows::fetch, NT threads) into a TileR16: x - centre and
 // its square, each split into hi/lo, 8-byte stores.
-template <int DP, int NT>
+template <int DP, int NT, int RDW = kRowDw, int SWZ = kSwz>
 struct TileStoreR16 {
-  using TR = TileR16<DP>;
+  using TR = TileR16<DP, RDW, SWZ>;
   using IO = TileIO16Rows<DP, NT>;
   template <class T, bool SPLIT>
   __device__ __forceinline__ static void store(uint16_t* hi_arr, uint16_t* lo_arr,
@@ -347,16 +350,18 @@ __device__ __forceinline__ s16x4 lds_read_tr16(const uint16_t* p) {
 // at rows 16 q + 4 h + e and 16 q + 8 + 4 h + e (e = 0..3).  Each lane addresses row
 // 16 q + 4 h + (i >> 2) (and + 8), features 32 b + 16 (j >> 4) + 4 (i & 3) .. + 3
 // (i = lane & 15); both rows' chunk swizzle is fixed by h, so the offsets are affine in q, b.
-struct TrOffsets {
+template <int RDW = kRowDw, int SWZ = kSwz>
+struct TrOffsetsL {
   int o1, o2;  // element offsets of the two reads for q = b = 0
-  __device__ __forceinline__ TrOffsets(int lane) {
+  __device__ __forceinline__ TrOffsetsL(int lane) {
     const int i = lane & 15, j = lane & 31, h = lane >> 5;
     const int cp = 2 * (j >> 4) + ((i & 3) >> 1);  // chunk within the block's four
     const int row = 4 * h + (i >> 2);
-    o1 = row * 2 * kRowDw + (cp ^ (h & kSwz)) * 8 + 4 * (i & 1);
-    o2 = (row + 8) * 2 * kRowDw + (cp ^ ((h + 2) & kSwz)) * 8 + 4 * (i & 1);
+    o1 = row * 2 * RDW + (cp ^ (h & SWZ)) * 8 + 4 * (i & 1);
+    o2 = (row + 8) * 2 * RDW + (cp ^ ((h + 2) & SWZ)) * 8 + 4 * (i & 1);
   }
 };
+using TrOffsets = TrOffsetsL<>;
 
 // Per interval: the two read bases of one array as LDS pointers.  The empty asm keeps the
 // compiler from hoisting every (q, b) address out of the loop (32 registers held across the
@@ -365,7 +370,8 @@ typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
 struct TrBase {
   lds_s16x4* p1;
   lds_s16x4* p2;
-  __device__ __forceinline__ TrBase(const uint16_t* arr, const TrOffsets& o) {
+  template <class O>
+  __device__ __forceinline__ TrBase(const uint16_t* arr, const O& o) {
     int o1 = o.o1, o2 = o.o2;
     asm volatile("" : "+v"(o1), "+v"(o2));
     p1 = (lds_s16x4*)(arr + o1);
@@ -373,9 +379,9 @@ struct TrBase {
   }
 };
 
-template <class V>
+template <class V, int RDW = kRowDw>
 __device__ __forceinline__ V tr_operand(const TrBase& t, int q, int b) {
-  const int d = (16 * q * 2 * kRowDw + 32 * b) / 4;  // in 8-byte units
+  const int d = (16 * q * 2 * RDW + 32 * b) / 4;  // in 8-byte units
   const s16x4 r1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(t.p1 + d);
   const s16x4 r2 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(t.p2 + d);
   const s16x4 both[2] = {r1, r2};
