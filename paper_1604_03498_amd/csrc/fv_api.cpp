@@ -321,8 +321,9 @@ hipError_t run_normext(const fv::Consts& c, int prec, const float* X, bool vec_o
 }
 
 // Component groups per chunk of the group-wise second pass (its workgroups have Wg waves, or 4
-// when Wg = 8 and DP > 64).
-int normext_groups(const fv::Consts& c) {
+// when Wg = 8 and DP > 64; the 16-bit forms' pipelined kernel covers 256 components).
+int normext_groups(const fv::Consts& c, int precision) {
+  if (precision != FV_PREC_FP32 && fv::normext16_pipelined(c)) return c.Kp / (8 * fv::kCompsPerWave);
   const int w = (c.DP > 64 && c.Wg == 8) ? 4 : c.Wg;
   return c.Kp / (fv::kCompsPerWave * w);
 }
@@ -948,7 +949,7 @@ SinglePlan plan_single(const fv_gmm* gmm, const fv::Consts& c, int64_t N, int pr
   p.grouped = c.Kp > fv::kFusedMaxK;
   if (N > 0)
     p.P = (path == Path::kFused) ? fused_single_chunk(N, gmm->device, c.Wg)
-          : p.grouped            ? normext_single_chunk(N, gmm->device, normext_groups(c))
+          : p.grouped            ? normext_single_chunk(N, gmm->device, normext_groups(c, precision))
                                  : split_single_chunk(N, gmm->device, slices, sliced_round(c, precision));
   p.n_items = N > 0 ? (int)((N + p.P - 1) / p.P) : 0;
   p.n_groups = (p.n_items + fv::kGroupItems - 1) / fv::kGroupItems;
@@ -1247,7 +1248,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
       const int tiles_cap = (int)((cp.rows + fv::kTile - 1) / fv::kTile);
       FV_HIP(run_lse(c2, precision, Fx, vec_ok, cp.rows, tiles_cap, grid_cap(resident), lse,
                      cp.rows, s));
-      const int groups = normext_groups(c);
+      const int groups = normext_groups(c, precision);
       const int grid2 = grid_cap(xcd_grid((device_cu_count(gmm->device) + groups - 1) / groups));
       FV_HIP(run_normext(c2, precision, Fx, vec_ok, cp.rows, P, ditems, cp.items, grid2, lse,
                          cp.rows, partials, s));
@@ -1536,7 +1537,7 @@ int fv_em_step(const fv_gmm* gmm, const float* X, int64_t N, int precision, floa
   // the second the per-chunk sums S0, S1, S2
   const bool grouped = c.Kp > fv::kFusedMaxK;
   const int slices = c.Kp / fv::kCompsPerWave;
-  const int P = grouped ? normext_single_chunk(N, gmm->device, normext_groups(c))
+  const int P = grouped ? normext_single_chunk(N, gmm->device, normext_groups(c, precision))
                         : split_single_chunk(N, gmm->device, slices, sliced_round(c, precision));
   const int n_items = (int)((N + P - 1) / P);
   const int G = fv::lse_groups(c);

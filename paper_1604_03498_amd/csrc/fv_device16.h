@@ -290,7 +290,7 @@ constexpr int kRowDw = 80;
 constexpr int kSwz = 3;
 template <int DP, int RDW = kRowDw, int SWZ = kSwz>
 struct TileR16 {
-  static_assert(DP <= 64, "two 64-feature halves at most");
+  static_assert(2 * DP <= 2 * RDW, "a row holds the 2*DP features");
   static constexpr int RS = 2 * RDW;       // elements per row
   static constexpr int kArr = kTile * RS;  // elements per array
   static constexpr int kSw = SWZ;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cstdlib>
 #include <stdint.h>
 
 #include <vector>
@@ -146,6 +147,15 @@ constexpr int kGroupItems = 16;
 
 inline size_t slot_floats(const Consts& c) { return (size_t)(2 * c.DP + 1) * c.Kp; }
 inline int lse_groups(const Consts& c) { return c.Kp / (kCompsPerWave * c.Wg); }
+
+// The 16-bit forms' group-wise second pass runs the pipelined specialised-wave kernel on groups
+// of 256 components (with the first pass's normalisers) when the model has whole groups and
+// DP <= 80; FV_NORMEXT16=w keeps the per-wave kernel (measurements).
+inline bool normext16_pipelined(const Consts& c) {
+  const char* e = std::getenv("FV_NORMEXT16");
+  if (e && e[0] == 'w') return false;
+  return c.Wg == kMaxWaves && c.DP <= 80 && c.Kp % (kMaxWaves * kCompsPerWave) == 0;
+}
 
 // Statistics kernel: for every item, the raw moments S0 = sum gamma, S1 = gamma^T X,
 // S2 = gamma^T X^2 of its rows go to partials[item] laid out [2*DP+1][Kp] (rows: x features,
