@@ -132,10 +132,14 @@ struct Workspace {
   std::mutex mu;
   char* dev = nullptr;
   size_t dev_cap = 0;
+  // Pinned staging of the batch tables: two halves of pin_cap bytes, filled by alternate calls,
+  // so that a call waits only for the sequence before the previous one to have read its half
+  // (the host builds the next batch's tables while the current one runs).
   char* pinned = nullptr;
   size_t pin_cap = 0;
-  hipEvent_t pin_done = nullptr;  // last H2D copy out of `pinned`
-  bool pin_pending = false;
+  int pin_half = 0;                             // the half the next call fills
+  hipEvent_t pin_done[2] = {nullptr, nullptr};  // end of the last sequence that read each half
+  bool pin_pending[2] = {false, false};
   std::vector<GraphEntry> graphs;  // most recent last
   fv::BatchCaps caps;  // of the batched sequence (grow by doubling, or set by batch_reserve)
   int64_t captures = 0, replays = 0;  // graph captures and replays on this stream
@@ -143,7 +147,7 @@ struct Workspace {
 
 std::atomic<int64_t> g_graph_captures{0}, g_graph_replays{0};
 
-constexpr size_t kMaxGraphs = 8;
+constexpr size_t kMaxGraphs = 16;
 
 void drop_graphs(Workspace* ws) {
   for (auto& g : ws->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -223,21 +227,28 @@ int ensure_dev(Workspace* ws, size_t need, hipStream_t s) {
 }
 
 int ensure_pinned(Workspace* ws, size_t need) {
-  if (ws->pin_pending) {
-    FV_HIP(hipEventSynchronize(ws->pin_done));
-    ws->pin_pending = false;
-  }
-  if (!ws->pin_done) FV_HIP(hipEventCreateWithFlags(&ws->pin_done, hipEventDisableTiming));
-  if (need <= ws->pin_cap) return FV_OK;
-  if (ws->pinned) {
+  if (need > ws->pin_cap && ws->pinned) {
+    for (int h = 0; h < 2; ++h)
+      if (ws->pin_pending[h]) {
+        FV_HIP(hipEventSynchronize(ws->pin_done[h]));
+        ws->pin_pending[h] = false;
+      }
     drop_graphs(ws);
     FV_HIP(hipHostFree(ws->pinned));
     ws->pinned = nullptr;
     ws->pin_cap = 0;
   }
-  size_t cap = align256(std::max(need, (size_t)(64u << 10)) * 2);
-  FV_HIP(hipHostMalloc(&ws->pinned, cap, hipHostMallocDefault));
-  ws->pin_cap = cap;
+  if (!ws->pinned) {
+    const size_t cap = align256(std::max(need, (size_t)(64u << 10)) * 2);
+    FV_HIP(hipHostMalloc(&ws->pinned, 2 * cap, hipHostMallocDefault));
+    ws->pin_cap = cap;
+  }
+  const int h = ws->pin_half;
+  if (ws->pin_pending[h]) {
+    FV_HIP(hipEventSynchronize(ws->pin_done[h]));
+    ws->pin_pending[h] = false;
+  }
+  if (!ws->pin_done[h]) FV_HIP(hipEventCreateWithFlags(&ws->pin_done[h], hipEventDisableTiming));
   return FV_OK;
 }
 
@@ -706,7 +717,8 @@ int fv_stream_release(int device, void* hip_stream) {
   drop_graphs(ws.get());
   if (ws->dev && (e = hipFree(ws->dev)) != hipSuccess) rc = hip_fail(e);
   if (ws->pinned && (e = hipHostFree(ws->pinned)) != hipSuccess) rc = hip_fail(e);
-  if (ws->pin_done) (void)hipEventDestroy(ws->pin_done);
+  for (hipEvent_t& ev : ws->pin_done)
+    if (ev) (void)hipEventDestroy(ev);
   ws->dev = ws->pinned = nullptr;
   return rc != FV_OK ? rc : rc_front;
 }
@@ -1184,7 +1196,8 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
 
   // work tables in pinned memory (same layout as on the device), then one H2D copy of the
   // whole capacity
-  char* pin = ws->pinned;
+  const int half = ws->pin_half;
+  char* pin = ws->pinned + (size_t)half * ws->pin_cap;
   fv::Counts* hcounts = reinterpret_cast<fv::Counts*>(pin);
   fv::Frame* hframes = reinterpret_cast<fv::Frame*>(pin + b_cnt);
   fv::Item* hitems = reinterpret_cast<fv::Item*>(pin + b_cnt + b_frames);
@@ -1228,7 +1241,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   // (grid = resident workgroups) or the two passes, then the finalize over the frame capacity
   // (slots past the batch exit at once).  Every grid depends on the capacities only.
   auto enqueue = [&]() -> int {
-    FV_HIP(hipMemcpyAsync(tab, ws->pinned, b_tab, hipMemcpyHostToDevice, s));
+    FV_HIP(hipMemcpyAsync(tab, pin, b_tab, hipMemcpyHostToDevice, s));
     if (pca) {
       hipEvent_t tp = timing_begin(s);
       FV_HIP(fv::launch_project(pca->p, Xd, cp.rows, ydev, project_grid(gmm->device, cp.rows),
@@ -1278,15 +1291,16 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   key.X = Xd;
   key.out = Od;
   key.dev = ws->dev;
-  key.pinned = ws->pinned;
+  key.pinned = pin;
   key.pca = pca ? pca->serial : 0;
   key.cap = grid_cap(1 << 30) == (1 << 30) ? 0 : grid_cap(1 << 30);
   key.grid = gmm->batch_grid;
   key.variant = gmm->fused16_variant + 4 * fused16_env();
   rc = run_sequence(ws, key, use_graph, s, enqueue);
   if (rc) return rc;
-  FV_HIP(hipEventRecord(ws->pin_done, s));
-  ws->pin_pending = true;
+  FV_HIP(hipEventRecord(ws->pin_done[half], s));
+  ws->pin_pending[half] = true;
+  ws->pin_half = half ^ 1;
   if (!(flags & FV_OUT_DEVICE))
     FV_HIP(hipMemcpyAsync(out, Od, (size_t)B * out_len * 4, hipMemcpyDeviceToHost, s));
   if (!(flags & FV_ASYNC)) FV_HIP(hipStreamSynchronize(s));

@@ -3,12 +3,17 @@
 // followed by the improved-FV assembly and normalisation (Fisher-information scaling,
 // signed square root, L2).
 //
-//   reduce_assemble  one workgroup per (64-component block, dimension d) of a frame; its three
-//                    waves sum the S1[d], S2[d] and S0 rows of the frame's slots in double:
-//                    within a chunk group (at most 16 consecutive slots) in index order, then
-//                    the group sums in order.  Then C1 = S1 - mu S0; C2 = S2 - 2 mu S1 +
-//                    mu^2 S0; u = C1 / sigma / (N sqrt w); v = (C2 / sigma^2 - S0) /
-//                    (N sqrt(2 w)); optional signed square root; the block's sum of squares
+//   reduce_assemble  one workgroup per (DB dimensions, KC components) of a frame, in two
+//                    shapes: DB = 4 and KC = 256 (nine waves, one per S1/S2/S0 row) when the
+//                    launch has enough such tiles, else DB = 1 and KC = 64 (one wave, four
+//                    rows of 16 lanes).  Each thread reads one row's 16-byte column of 4
+//                    components from the frame's slots (all of a chunk group's loads in
+//                    flight together) and sums it in double: within a chunk group (at most 16
+//                    consecutive slots) in index order, then the group sums in order.  Then,
+//                    one thread per component, C1 = S1 - mu S0; C2 = S2 - 2 mu S1 + mu^2 S0;
+//                    u = C1 / sigma / (N sqrt w); v = (C2 / sigma^2 - S0) / (N sqrt(2 w));
+//                    optional signed square root; per dimension, a wave's sum of squares over
+//                    its 64 components.  Both shapes give the same bits.
 //   l2               phi /= ||phi||_2 (skipped when the norm is 0)
 // Every sum has a fixed order that depends only on the frame's own chunking, so a frame's
 // result is bitwise independent of the other frames in a batch.
@@ -23,100 +28,130 @@ constexpr unsigned kFlagNoPower = 4u;
 constexpr unsigned kFlagNoL2 = 8u;
 constexpr int kThreads = 256;
 constexpr int kL2PerThread = 4;
-constexpr int kCompBlock = 64;   // components per reduce_assemble workgroup (one per lane)
-constexpr int kRedThreads = 192; // three waves: S1 row, S2 row, S0 row
-
-// Loads of one group's slots for one (row, component), unconditional so that all of them are
-// in flight together: slot indices are clamped to [0, nclamp) (nclamp >= 1 valid slots from p)
-// and values past n (or for a padded component) are replaced by +0.0, which leaves the
-// index-order double sum unchanged (the sum never holds -0.0).
-__device__ inline void load_group(const float* __restrict__ p, int nclamp, int n, size_t slot,
-                                  bool ok, float (&v)[kGroupItems]) {
+// Index-order double sums of one chunk group's n (1..16) slots of a 16-byte column, with
+// U >= n loads issued together: unconditional, slot index clamped to the group, and values of
+// slots past the group (or of a row that is not read, ok false) replaced by +0.0, which leaves
+// the sum unchanged (it never holds -0.0).  The loads must not sit behind per-slot branches,
+// which would serialise them.
+// The slot base address is uniform over the workgroup and the thread's byte offset into the
+// slot is 32-bit: buffer loads with a scalar resource per slot and a 32-bit vector offset.
+template <int U>
+__device__ inline void sum_group(const float* __restrict__ partials, uint32_t lbytes, int i0,
+                                 int n, size_t slot, bool ok, double (&a)[4]) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 v[U];
 #pragma unroll
-  for (int i = 0; i < kGroupItems; ++i) v[i] = p[(size_t)min(i, nclamp - 1) * slot];
+  for (int u = 0; u < U; ++u) {
+    const float* sp = partials + (size_t)(i0 + min(u, n - 1)) * slot;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(sp), 0, (int)(slot * 4), 0x00020000);
+    v[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)lbytes, 0, 0);
+  }
 #pragma unroll
-  for (int i = 0; i < kGroupItems; ++i) v[i] = (ok && i < n) ? v[i] : 0.f;
+  for (int u = 0; u < U; ++u) {
+    const bool in = ok && u < n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] += in ? (double)__uint_as_float(v[u][q]) : 0.0;
+  }
 }
 
-__device__ inline double sum_group(const float (&v)[kGroupItems]) {
-  double a = 0.0;
-#pragma unroll
-  for (int i = 0; i < kGroupItems; ++i) a += (double)v[i];
-  return a;
-}
+// Waves of a reduce_assemble workgroup: 2 DB + 1 rows, 64 / (KC / 4) rows per wave.
+constexpr int red_waves(int DB, int KC) { return (2 * DB + 1 + 64 / (KC / 4) - 1) / (64 / (KC / 4)); }
 
-__global__ __launch_bounds__(kRedThreads) void reduce_assemble_kernel(
+template <int DB, int KC>
+__global__ __launch_bounds__(64 * red_waves(DB, KC)) __attribute__((amdgpu_waves_per_eu(5)))
+void reduce_assemble_kernel(
     const float* __restrict__ partials, const Frame* __restrict__ frames, Frame single,
-    const Group* __restrict__ groups, int K, int D, int DP, int Kp, int nkb,
+    const Group* __restrict__ groups, int K, int D, int DP, int Kp, int nkc, int nkb,
     const double* __restrict__ mu64, const double* __restrict__ isd64,
     const double* __restrict__ ivar64, const double* __restrict__ cu64,
     const double* __restrict__ cv64, unsigned flags, float* __restrict__ out,
     double* __restrict__ normpart, const Counts* __restrict__ cnt) {
-  __shared__ double sv[3][kCompBlock];
+  constexpr int R = 2 * DB + 1;     // rows: S1[d0 + i], S2[d0 + i], S0
+  constexpr int NC4 = KC / 4;       // 16-byte columns per row
+  constexpr int RPW = 64 / NC4;     // rows per wave
+  __shared__ double sv[R][KC];
   const int b = blockIdx.y;
   if (cnt && b >= cnt->B) return;  // a frame slot past the batch (grid sized to a capacity)
   const Frame fr = frames != nullptr ? frames[b] : single;
-  const int kb = blockIdx.x % nkb;
-  const int d = blockIdx.x / nkb;
-  const int wv = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int k = kb * kCompBlock + lane;
-  const bool kok = k < K;
+  const int kc = blockIdx.x % nkc;
+  const int d0 = (blockIdx.x / nkc) * DB;
+  const int t = threadIdx.x;
+  const int col = t % NC4;
+  const int r = t / NC4;            // this thread's row
+  const int i = r < DB ? r : r - DB;
+  const int kcol = kc * KC + 4 * col;
+  const bool rok = r < R && kcol < Kp && (r == 2 * DB || d0 + i < D);
+  const int prow = r == 2 * DB ? 2 * DP : (r < DB ? d0 + r : DP + d0 + i);
+  const uint32_t lbytes = rok ? (uint32_t)(prow * Kp + kcol) * 4u : 0u;  // bytes into a slot
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
-  const int row = wv == 0 ? d : (wv == 1 ? DP + d : 2 * DP);
-  const float* base = partials + (size_t)row * Kp + (kok ? k : 0);
-  // the finalize constants of (k, d), loaded up front so that their latency overlaps the sums
-  const int kd = (kok ? k : 0) * D + d;
-  double mu = 0.0, isd = 0.0, ivar = 0.0, cu = 0.0, cv = 0.0;
-  if (wv == 0) {
-    mu = mu64[kd];
-    isd = isd64[kd];
-    ivar = ivar64[kd];
-    cu = cu64[kok ? k : 0];
-    cv = cv64[kok ? k : 0];
+
+  // a chunk group's (first slot, slot count); with a group table the next entry is loaded
+  // while the current group's slots are in flight
+  auto group_at = [&](int g) -> Group {
+    if (groups != nullptr) return groups[fr.group0 + g];
+    const int i0 = fr.item0 + g * kGroupItems;
+    return Group{i0, min(kGroupItems, fr.item0 + fr.nitems - i0)};
+  };
+  // the narrow shape (single frames, latency-bound) also loads its constants up front
+  const int kq = kc * KC + t;
+  const bool pre = DB == 1 && t < KC && kq < K && d0 < D;
+  double mu_p = 0.0, isd_p = 0.0, ivar_p = 0.0, cu_p = 0.0, cv_p = 0.0;
+  if (pre) {
+    const int kd = kq * D + d0;
+    mu_p = mu64[kd];
+    isd_p = isd64[kd];
+    ivar_p = ivar64[kd];
+    cu_p = cu64[kq];
+    cv_p = cv64[kq];
   }
 
-  double tot = 0.0;
-  for (int g = 0; g < fr.ngroups; g += 2) {
-    int i0a, na, i0b = 0, nb = 0;
-    if (groups != nullptr) {
-      const Group ga = groups[fr.group0 + g];
-      i0a = ga.item0;
-      na = ga.nitems;
-      if (g + 1 < fr.ngroups) {
-        const Group gb = groups[fr.group0 + g + 1];
-        i0b = gb.item0;
-        nb = gb.nitems;
-      }
-    } else {
-      i0a = fr.item0 + g * kGroupItems;
-      na = min(kGroupItems, fr.item0 + fr.nitems - i0a);
-      if (g + 1 < fr.ngroups) {
-        i0b = i0a + kGroupItems;
-        nb = min(kGroupItems, fr.item0 + fr.nitems - i0b);
-      }
-    }
-    float va[kGroupItems], vb[kGroupItems];
-    load_group(base + (size_t)i0a * slot, na, na, slot, kok, va);
-    if (nb > 0)
-      load_group(base + (size_t)i0b * slot, nb, nb, slot, kok, vb);
-    else
-      load_group(base + (size_t)i0a * slot, na, 0, slot, kok, vb);
-    tot += sum_group(va);
-    if (g + 1 < fr.ngroups) tot += sum_group(vb);
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  Group cur = fr.ngroups > 0 ? group_at(0) : Group{0, 0};
+  for (int g = 0; g < fr.ngroups; ++g) {
+    const Group nxt = g + 1 < fr.ngroups ? group_at(g + 1) : cur;
+    // uniform over the workgroup: scalar registers, so the slot bases are scalar too
+    const int i0 = __builtin_amdgcn_readfirstlane(cur.item0);
+    const int n = __builtin_amdgcn_readfirstlane(cur.nitems);
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (n > 8)
+      sum_group<16>(partials, lbytes, i0, n, slot, rok, a);
+    else if (n > 4)
+      sum_group<8>(partials, lbytes, i0, n, slot, rok, a);
+    else if (n > 0)
+      sum_group<4>(partials, lbytes, i0, n, slot, rok, a);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tot[q] += a[q];
+    cur = nxt;
   }
-  sv[wv][lane] = tot;
+  if (r < R)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sv[r][4 * col + q] = tot[q];
   __syncthreads();
-  if (wv != 0) return;
 
-  double ss = 0.0;
-  if (kok) {
-    const double S0 = sv[2][lane], S1 = sv[0][lane], S2 = sv[1][lane];
+  // one thread per component (the first KC / 64 waves): u and v of the DB dimensions
+  if (t >= KC) return;
+  const int k = kc * KC + t;
+  const bool kok = k < K;
+  const int KD = K * D;
+  float* o = out + (size_t)b * 2 * KD + (size_t)(kok ? k : 0) * D + d0;
+  const double S0 = sv[2 * DB][t];
+  const double invN = fr.nrows > 0 ? 1.0 / (double)fr.nrows : 0.0;
+  const double cu = DB == 1 ? cu_p : (kok ? cu64[k] : 0.0);
+  const double cv = DB == 1 ? cv_p : (kok ? cv64[k] : 0.0);
+  float uo[DB], vo[DB];
+  double ss[DB];
+#pragma unroll
+  for (int j = 0; j < DB; ++j) {
     double u = 0.0, v = 0.0;
-    if (fr.nrows > 0) {
+    if (kok && d0 + j < D && fr.nrows > 0) {
+      const int kd = k * D + d0 + j;
+      const double mu = DB == 1 ? mu_p : mu64[kd];
+      const double isd = DB == 1 ? isd_p : isd64[kd];
+      const double ivar = DB == 1 ? ivar_p : ivar64[kd];
+      const double S1 = sv[j][t], S2 = sv[DB + j][t];
       const double C1 = S1 - mu * S0;                    // sum gamma (x - mu)
       const double C2 = S2 - mu * (2.0 * S1 - mu * S0);  // sum gamma (x - mu)^2
-      const double invN = 1.0 / (double)fr.nrows;
       u = C1 * isd * cu * invN;
       v = (C2 * ivar - S0) * cv * invN;
       if (!(flags & kFlagNoPower)) {
@@ -124,16 +159,34 @@ __global__ __launch_bounds__(kRedThreads) void reduce_assemble_kernel(
         v = (v > 0.0) ? sqrt(v) : ((v < 0.0) ? -sqrt(-v) : 0.0);
       }
     }
-    const int KD = K * D;
-    float* o = out + (size_t)b * 2 * KD;
-    o[k * D + d] = (float)u;
-    o[KD + k * D + d] = (float)v;
-    ss = u * u + v * v;
+    uo[j] = (float)u;
+    vo[j] = (float)v;
+    ss[j] = u * u + v * v;
   }
-  // fixed-order butterfly over the wave
+  if (kok) {
+    if (DB == 4 && D % 4 == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+      *reinterpret_cast<float4*>(o) = make_float4(uo[0], uo[1], uo[2], uo[3]);
+      *reinterpret_cast<float4*>(o + KD) = make_float4(vo[0], vo[1], vo[2], vo[3]);
+    } else {
 #pragma unroll
-  for (int m = 32; m > 0; m >>= 1) ss += __shfl_xor(ss, m);
-  if (lane == 0) normpart[(size_t)b * gridDim.x + blockIdx.x] = ss;
+      for (int j = 0; j < DB; ++j)
+        if (d0 + j < D) {
+          o[j] = uo[j];
+          o[KD + j] = vo[j];
+        }
+    }
+  }
+  // per dimension, a fixed-order butterfly over the wave's 64 components (the same in both
+  // workgroup shapes); lane 0 writes the (dimension, 64-component block) partial of the norm
+  const int kb = (kc * KC + (t & ~63)) / 64;
+#pragma unroll
+  for (int j = 0; j < DB; ++j) {
+    double x = ss[j];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m);
+    if ((t & 63) == 0 && kb < nkb && d0 + j < D)
+      normpart[((size_t)b * D + d0 + j) * nkb + kb] = x;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void l2_kernel(float* __restrict__ out,
@@ -172,17 +225,28 @@ __global__ __launch_bounds__(kThreads) void l2_kernel(float* __restrict__ out,
 
 }  // namespace
 
-int finalize_blocks(const Consts& c) { return ((c.K + kCompBlock - 1) / kCompBlock) * c.D; }
+int finalize_blocks(const Consts& c) { return c.D * ((c.K + 63) / 64); }
 
 hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* frames,
                            Frame single, int B, const Group* groups, unsigned flags, float* out,
                            double* normpart, hipStream_t stream) {
   if (B <= 0) return hipSuccess;
   const int nblk = finalize_blocks(c);
-  const int nkb = (c.K + kCompBlock - 1) / kCompBlock;
-  hipLaunchKernelGGL(reduce_assemble_kernel, dim3(nblk, B), dim3(kRedThreads), 0, stream, partials,
-                     frames, single, groups, c.K, c.D, c.DP, c.Kp, nkb, c.mu64, c.isd64, c.ivar64,
-                     c.cu64, c.cv64, flags, out, normpart, c.cnt);
+  const int nkb = (c.K + 63) / 64;
+  // the wide shape when its tiles alone give at least two workgroups per CU, else the narrow one
+  const int nkc_w = (c.Kp + 255) / 256, ndb_w = (c.D + 3) / 4;
+  if ((int64_t)B * nkc_w * ndb_w >= 512) {
+    hipLaunchKernelGGL((reduce_assemble_kernel<4, 256>), dim3(nkc_w * ndb_w, B),
+                       dim3(64 * red_waves(4, 256)), 0, stream, partials, frames, single, groups,
+                       c.K, c.D, c.DP, c.Kp, nkc_w, nkb, c.mu64, c.isd64, c.ivar64, c.cu64,
+                       c.cv64, flags, out, normpart, c.cnt);
+  } else {
+    const int nkc_n = (c.Kp + 63) / 64;
+    hipLaunchKernelGGL((reduce_assemble_kernel<1, 64>), dim3(nkc_n * c.D, B),
+                       dim3(64 * red_waves(1, 64)), 0, stream, partials, frames, single, groups,
+                       c.K, c.D, c.DP, c.Kp, nkc_n, nkb, c.mu64, c.isd64, c.ivar64, c.cu64,
+                       c.cv64, flags, out, normpart, c.cnt);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!(flags & kFlagNoL2)) {
