@@ -530,11 +530,11 @@ int project_grid(int device, int64_t N) {
 
 // Byte layout of a stream's batch workspace for capacities `cp`: partial slots, finalize
 // norm parts, first-pass normalisers (two-pass path), the work table (Counts record, frames,
-// items, groups), staging of host X and host out, and the projected rows.
+// items, item order), staging of host X and host out, and the projected rows.
 struct BatchLayout {
-  size_t part = 0, norm = 0, lse = 0, cnt = 0, frames = 0, items = 0, groups = 0, order = 0;
+  size_t part = 0, norm = 0, lse = 0, cnt = 0, frames = 0, items = 0, order = 0;
   size_t x = 0, out = 0, y = 0;
-  size_t tab() const { return cnt + frames + items + groups + order; }
+  size_t tab() const { return cnt + frames + items + order; }
   size_t total() const { return part + norm + lse + tab() + x + out + y; }
 };
 
@@ -548,7 +548,6 @@ BatchLayout batch_layout(const fv::Consts& c, Path path, const fv::BatchCaps& cp
   l.cnt = align256(sizeof(fv::Counts));
   l.frames = align256((size_t)cp.B * sizeof(fv::Frame));
   l.items = align256((size_t)cp.items * sizeof(fv::Item));
-  l.groups = align256((size_t)cp.groups * sizeof(fv::Group));
   l.order = align256((size_t)cp.items * sizeof(int32_t));
   l.x = (flags & FV_X_DEVICE) ? 0 : align256((size_t)cp.rows * Din * 4);
   l.out = (flags & FV_OUT_DEVICE) ? 0 : align256((size_t)cp.B * out_len * 4);
@@ -1081,7 +1080,7 @@ static int encode_impl(const fv_gmm* gmm, const fv_pca* pca, const float* X, int
     }
     fv::Frame single{N, 0, n_items, 0, n_groups};
     hipEvent_t t1 = ext ? nullptr : timing_begin(s);
-    FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, nullptr, flags, Od, normpart, s));
+    FV_HIP(fv::launch_finalize(c, partials, nullptr, single, 1, flags, Od, normpart, s));
     timing_end(t1, 1, s);
     return FV_OK;
   };
@@ -1145,7 +1144,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
     const int64_t n = offsets[b + 1] - offsets[b];
     const int64_t ni = (n + P - 1) / P;
     const int64_t ng = (ni + fv::kGroupItems - 1) / fv::kGroupItems;
-    frames[b] = fv::Frame{n, (int32_t)n_items64, (int32_t)ni, (int32_t)n_groups64, (int32_t)ng};
+    frames[b] = fv::Frame{n, (int32_t)n_items64, (int32_t)ni, b, (int32_t)ng};
     n_items64 += ni;
     n_groups64 += ng;
   }
@@ -1172,7 +1171,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   const size_t out_len = (size_t)2 * c.K * c.D;
   const BatchLayout lay = batch_layout(c, path, cp, Din, flags, pca != nullptr);
   const size_t b_part = lay.part, b_norm = lay.norm, b_lse = lay.lse, b_cnt = lay.cnt;
-  const size_t b_frames = lay.frames, b_items = lay.items, b_groups = lay.groups;
+  const size_t b_frames = lay.frames, b_items = lay.items;
   const size_t b_tab = lay.tab();
   const size_t b_x = lay.x, b_out = lay.out, b_y = lay.y;
   int rc = ensure_dev(ws, b_part + b_norm + b_lse + b_tab + b_x + b_out + b_y, s);
@@ -1187,9 +1186,7 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   const fv::Counts* dcounts = reinterpret_cast<const fv::Counts*>(tab);
   fv::Frame* dframes = reinterpret_cast<fv::Frame*>(tab + b_cnt);
   fv::Item* ditems = reinterpret_cast<fv::Item*>(tab + b_cnt + b_frames);
-  fv::Group* dgroups = reinterpret_cast<fv::Group*>(tab + b_cnt + b_frames + b_items);
-  const int32_t* dorder =
-      reinterpret_cast<const int32_t*>(tab + b_cnt + b_frames + b_items + b_groups);
+  const int32_t* dorder = reinterpret_cast<const int32_t*>(tab + b_cnt + b_frames + b_items);
   float* xdev = reinterpret_cast<float*>(tab + b_tab);
   float* odev = reinterpret_cast<float*>(tab + b_tab + b_x);
   float* ydev = reinterpret_cast<float*>(tab + b_tab + b_x + b_out);
@@ -1201,22 +1198,21 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
   fv::Counts* hcounts = reinterpret_cast<fv::Counts*>(pin);
   fv::Frame* hframes = reinterpret_cast<fv::Frame*>(pin + b_cnt);
   fv::Item* hitems = reinterpret_cast<fv::Item*>(pin + b_cnt + b_frames);
-  fv::Group* hgroups = reinterpret_cast<fv::Group*>(pin + b_cnt + b_frames + b_items);
-  int32_t* horder = reinterpret_cast<int32_t*>(pin + b_cnt + b_frames + b_items + b_groups);
+  int32_t* horder = reinterpret_cast<int32_t*>(pin + b_cnt + b_frames + b_items);
   *hcounts = fv::Counts{rows, n_items, (int32_t)((rows + fv::kTile - 1) / fv::kTile), B, 0};
-  std::memcpy(hframes, frames.data(), (size_t)B * sizeof(fv::Frame));
+  // the finalize takes the frames with the most slots first (its longest workgroups start
+  // first); each record keeps the frame's index in the batch
+  for (int b = 0; b < B; ++b) hframes[b] = frames[b];
+  std::stable_sort(hframes, hframes + B, [](const fv::Frame& a, const fv::Frame& b) {
+    return a.nitems > b.nitems;
+  });
   {
-    int64_t i = 0, gi = 0;
+    int64_t i = 0;
     for (int b = 0; b < B; ++b) {
       for (int32_t q = 0; q < frames[b].nitems; ++q, ++i) {
         const int64_t r0 = (int64_t)q * P;
         const int64_t nr = std::min<int64_t>(P, frames[b].nrows - r0);
         hitems[i] = fv::Item{offsets[b] + r0, (int32_t)nr, 0};
-      }
-      for (int32_t q = 0; q < frames[b].ngroups; ++q, ++gi) {
-        const int32_t i0 = frames[b].item0 + q * fv::kGroupItems;
-        const int32_t ni = std::min<int32_t>(fv::kGroupItems, frames[b].item0 + frames[b].nitems - i0);
-        hgroups[gi] = fv::Group{i0, ni};
       }
     }
     // the statistics launch takes the items largest first (full chunks, then every frame's
@@ -1268,8 +1264,8 @@ static int encode_batch_impl(const fv_gmm* gmm, const fv_pca* pca, const float* 
     }
     timing_end(t0, 0, s);
     hipEvent_t t1 = timing_begin(s);
-    FV_HIP(fv::launch_finalize(cc, partials, dframes, fv::Frame{0, 0, 0, 0, 0}, cp.B, dgroups,
-                               flags, Od, normpart, s));
+    FV_HIP(fv::launch_finalize(cc, partials, dframes, fv::Frame{0, 0, 0, 0, 0}, cp.B, flags, Od,
+                               normpart, s));
     timing_end(t1, 1, s);
     return FV_OK;
   };

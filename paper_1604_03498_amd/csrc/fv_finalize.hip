@@ -5,11 +5,12 @@
 //
 //   reduce_assemble  one workgroup per (DB dimensions, KC components) of a frame, in two
 //                    shapes: DB = 4 and KC = 256 (nine waves, one per S1/S2/S0 row) when the
-//                    launch has enough such tiles, else DB = 1 and KC = 64 (one wave, four
-//                    rows of 16 lanes).  Each thread reads one row's 16-byte column of 4
-//                    components from the frame's slots (all of a chunk group's loads in
-//                    flight together) and sums it in double: within a chunk group (at most 16
-//                    consecutive slots) in index order, then the group sums in order.  Then,
+//                    launch has enough such tiles, else DB = 1 and KC = 64 (three waves).
+//                    Each thread reads one row's column of 4 components (wide) or 1 (narrow)
+//                    from the frame's slots (all loads of a chunk group, two groups in the
+//                    narrow shape, in flight together) and sums it in double:
+//                    within a chunk group (at most 16 consecutive slots) in index order, then
+//                    the group sums in order.  A batch's frames come longest first.  Then,
 //                    one thread per component, C1 = S1 - mu S0; C2 = S2 - 2 mu S1 + mu^2 S0;
 //                    u = C1 / sigma / (N sqrt w); v = (C2 / sigma^2 - S0) / (N sqrt(2 w));
 //                    optional signed square root; per dimension, a wave's sum of squares over
@@ -28,68 +29,121 @@ constexpr unsigned kFlagNoPower = 4u;
 constexpr unsigned kFlagNoL2 = 8u;
 constexpr int kThreads = 256;
 constexpr int kL2PerThread = 4;
-// Index-order double sums of one chunk group's n (1..16) slots of a 16-byte column, with
-// U >= n loads issued together: unconditional, slot index clamped to the group, and values of
-// slots past the group (or of a row that is not read, ok false) replaced by +0.0, which leaves
-// the sum unchanged (it never holds -0.0).  The loads must not sit behind per-slot branches,
-// which would serialise them.
-// The slot base address is uniform over the workgroup and the thread's byte offset into the
-// slot is 32-bit: buffer loads with a scalar resource per slot and a 32-bit vector offset.
-template <int U>
-__device__ inline void sum_group(const float* __restrict__ partials, uint32_t lbytes, int i0,
-                                 int n, size_t slot, bool ok, double (&a)[4]) {
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  u32x4 v[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const float* sp = partials + (size_t)(i0 + min(u, n - 1)) * slot;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(sp), 0, (int)(slot * 4), 0x00020000);
-    v[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)lbytes, 0, 0);
+// A thread's column of CPL consecutive components (CPL = 4: 16 bytes, or 1) in one slot.  The
+// slot base address is uniform over the workgroup and the thread's byte offset into the slot
+// is 32-bit: a buffer load with a scalar resource per slot and a 32-bit vector offset.
+template <int CPL> struct Col;
+template <> struct Col<4> {
+  typedef unsigned int T __attribute__((ext_vector_type(4)));
+  static __device__ inline T load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
   }
+  static __device__ inline float at(const T& v, int q) { return __uint_as_float(v[q]); }
+};
+template <> struct Col<1> {
+  typedef unsigned int T;
+  static __device__ inline T load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+  }
+  static __device__ inline float at(const T& v, int) { return __uint_as_float(v); }
+};
+
+template <int CPL>
+__device__ inline typename Col<CPL>::T load_col(const float* __restrict__ partials, int idx,
+                                                size_t slot, uint32_t lbytes) {
+  const float* sp = partials + (size_t)idx * slot;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(sp), 0, (int)(slot * 4), 0x00020000);
+  return Col<CPL>::load(rs, lbytes);
+}
+
+// Index-order double sums of one chunk group's n (1..16) slots, with U >= n loads issued
+// together: unconditional, slot index clamped to the group, and values of slots past the group
+// (or of a row that is not read, ok false) replaced by +0.0, which leaves the sum unchanged (it
+// never holds -0.0).  The loads must not sit behind per-slot branches, which would serialise
+// them.
+template <int U, int CPL>
+__device__ inline void sum_group(const float* __restrict__ partials, uint32_t lbytes, int i0,
+                                 int n, size_t slot, bool ok, double (&a)[CPL]) {
+  typename Col<CPL>::T v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) v[u] = load_col<CPL>(partials, i0 + min(u, n - 1), slot, lbytes);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const bool in = ok && u < n;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] += in ? (double)__uint_as_float(v[u][q]) : 0.0;
+    for (int q = 0; q < CPL; ++q) a[q] += in ? (double)Col<CPL>::at(v[u], q) : 0.0;
   }
 }
 
-// Waves of a reduce_assemble workgroup: 2 DB + 1 rows, 64 / (KC / 4) rows per wave.
-constexpr int red_waves(int DB, int KC) { return (2 * DB + 1 + 64 / (KC / 4) - 1) / (64 / (KC / 4)); }
+// Two consecutive chunk groups (na in 1..16 and nb in 0..16 slots) with all 32 loads issued
+// together, then each group's index-order sum added to tot in order: the same sums as
+// sum_group on each group in turn.  (Without a second group, nb = 0: its sum is +0.0 and adding
+// it changes nothing; there is no branch, so that all loads stay ahead of the sums.)
+template <int CPL>
+__device__ inline void sum_two_groups(const float* __restrict__ partials, uint32_t lbytes,
+                                      Group ga, Group gb, size_t slot, bool ok,
+                                      double (&tot)[CPL]) {
+  typename Col<CPL>::T v[2 * kGroupItems];
+#pragma unroll
+  for (int u = 0; u < 2 * kGroupItems; ++u) {
+    const int idx = u < kGroupItems ? ga.item0 + min(u, ga.nitems - 1)
+                                    : (gb.nitems > 0 ? gb.item0 + min(u - kGroupItems, gb.nitems - 1)
+                                                     : ga.item0);
+    v[u] = load_col<CPL>(partials, idx, slot, lbytes);
+  }
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const int n = half == 0 ? ga.nitems : gb.nitems;
+    double a[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) a[q] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kGroupItems; ++u) {
+      const bool in = ok && u < n;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q)
+        a[q] += in ? (double)Col<CPL>::at(v[half * kGroupItems + u], q) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) tot[q] += a[q];
+  }
+}
 
-template <int DB, int KC>
-__global__ __launch_bounds__(64 * red_waves(DB, KC)) __attribute__((amdgpu_waves_per_eu(5)))
-void reduce_assemble_kernel(
+// Waves of a reduce_assemble workgroup: 2 DB + 1 rows of KC / CPL columns, 64 columns a wave.
+constexpr int red_waves(int DB, int KC, int CPL) {
+  return (2 * DB + 1 + 64 / (KC / CPL) - 1) / (64 / (KC / CPL));
+}
+
+template <int DB, int KC, int CPL>
+__global__ __launch_bounds__(64 * red_waves(DB, KC, CPL))
+__attribute__((amdgpu_waves_per_eu(DB == 1 ? 1 : 5))) void reduce_assemble_kernel(
     const float* __restrict__ partials, const Frame* __restrict__ frames, Frame single,
-    const Group* __restrict__ groups, int K, int D, int DP, int Kp, int nkc, int nkb,
+    int K, int D, int DP, int Kp, int nkc, int nkb,
     const double* __restrict__ mu64, const double* __restrict__ isd64,
     const double* __restrict__ ivar64, const double* __restrict__ cu64,
     const double* __restrict__ cv64, unsigned flags, float* __restrict__ out,
     double* __restrict__ normpart, const Counts* __restrict__ cnt) {
   constexpr int R = 2 * DB + 1;     // rows: S1[d0 + i], S2[d0 + i], S0
-  constexpr int NC4 = KC / 4;       // 16-byte columns per row
-  constexpr int RPW = 64 / NC4;     // rows per wave
+  constexpr int NC = KC / CPL;      // columns per row
   __shared__ double sv[R][KC];
-  const int b = blockIdx.y;
-  if (cnt && b >= cnt->B) return;  // a frame slot past the batch (grid sized to a capacity)
-  const Frame fr = frames != nullptr ? frames[b] : single;
+  if (cnt && (int)blockIdx.y >= cnt->B) return;  // past the batch (grid sized to a capacity)
+  const Frame fr = frames != nullptr ? frames[blockIdx.y] : single;
+  const int b = frames != nullptr ? fr.index : 0;  // the frame's output row and norm parts
   const int kc = blockIdx.x % nkc;
   const int d0 = (blockIdx.x / nkc) * DB;
   const int t = threadIdx.x;
-  const int col = t % NC4;
-  const int r = t / NC4;            // this thread's row
+  const int col = t % NC;
+  const int r = t / NC;             // this thread's row
   const int i = r < DB ? r : r - DB;
-  const int kcol = kc * KC + 4 * col;
+  const int kcol = kc * KC + CPL * col;
   const bool rok = r < R && kcol < Kp && (r == 2 * DB || d0 + i < D);
   const int prow = r == 2 * DB ? 2 * DP : (r < DB ? d0 + r : DP + d0 + i);
   const uint32_t lbytes = rok ? (uint32_t)(prow * Kp + kcol) * 4u : 0u;  // bytes into a slot
   const size_t slot = (size_t)(2 * DP + 1) * Kp;
 
-  // a chunk group's (first slot, slot count); with a group table the next entry is loaded
-  // while the current group's slots are in flight
+  // a chunk group's (first slot, slot count)
   auto group_at = [&](int g) -> Group {
-    if (groups != nullptr) return groups[fr.group0 + g];
     const int i0 = fr.item0 + g * kGroupItems;
     return Group{i0, min(kGroupItems, fr.item0 + fr.nitems - i0)};
   };
@@ -106,27 +160,45 @@ void reduce_assemble_kernel(
     cv_p = cv64[kq];
   }
 
-  double tot[4] = {0.0, 0.0, 0.0, 0.0};
-  Group cur = fr.ngroups > 0 ? group_at(0) : Group{0, 0};
-  for (int g = 0; g < fr.ngroups; ++g) {
-    const Group nxt = g + 1 < fr.ngroups ? group_at(g + 1) : cur;
-    // uniform over the workgroup: scalar registers, so the slot bases are scalar too
-    const int i0 = __builtin_amdgcn_readfirstlane(cur.item0);
-    const int n = __builtin_amdgcn_readfirstlane(cur.nitems);
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    if (n > 8)
-      sum_group<16>(partials, lbytes, i0, n, slot, rok, a);
-    else if (n > 4)
-      sum_group<8>(partials, lbytes, i0, n, slot, rok, a);
-    else if (n > 0)
-      sum_group<4>(partials, lbytes, i0, n, slot, rok, a);
+  double tot[CPL];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) tot[q] += a[q];
-    cur = nxt;
+  for (int q = 0; q < CPL; ++q) tot[q] = 0.0;
+  if constexpr (DB == 1) {
+    // the narrow shape: two groups' slots in flight at a time (registers are plentiful at one
+    // wave per workgroup)
+    for (int g = 0; g < fr.ngroups; g += 2) {
+      Group ga = group_at(g);
+      Group gb = g + 1 < fr.ngroups ? group_at(g + 1) : Group{0, 0};
+      ga.item0 = __builtin_amdgcn_readfirstlane(ga.item0);
+      ga.nitems = __builtin_amdgcn_readfirstlane(ga.nitems);
+      gb.item0 = __builtin_amdgcn_readfirstlane(gb.item0);
+      gb.nitems = __builtin_amdgcn_readfirstlane(gb.nitems);
+      if (ga.nitems > 0) sum_two_groups<CPL>(partials, lbytes, ga, gb, slot, rok, tot);
+    }
+  } else {
+    Group cur = fr.ngroups > 0 ? group_at(0) : Group{0, 0};
+    for (int g = 0; g < fr.ngroups; ++g) {
+      const Group nxt = g + 1 < fr.ngroups ? group_at(g + 1) : cur;
+      // uniform over the workgroup: scalar registers, so the slot bases are scalar too
+      const int i0 = __builtin_amdgcn_readfirstlane(cur.item0);
+      const int n = __builtin_amdgcn_readfirstlane(cur.nitems);
+      double a[CPL];
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) a[q] = 0.0;
+      if (n > 8)
+        sum_group<16, CPL>(partials, lbytes, i0, n, slot, rok, a);
+      else if (n > 4)
+        sum_group<8, CPL>(partials, lbytes, i0, n, slot, rok, a);
+      else if (n > 0)
+        sum_group<4, CPL>(partials, lbytes, i0, n, slot, rok, a);
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) tot[q] += a[q];
+      cur = nxt;
+    }
   }
   if (r < R)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sv[r][4 * col + q] = tot[q];
+    for (int q = 0; q < CPL; ++q) sv[r][CPL * col + q] = tot[q];
   __syncthreads();
 
   // one thread per component (the first KC / 64 waves): u and v of the DB dimensions
@@ -228,22 +300,22 @@ __global__ __launch_bounds__(kThreads) void l2_kernel(float* __restrict__ out,
 int finalize_blocks(const Consts& c) { return c.D * ((c.K + 63) / 64); }
 
 hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* frames,
-                           Frame single, int B, const Group* groups, unsigned flags, float* out,
-                           double* normpart, hipStream_t stream) {
+                           Frame single, int B, unsigned flags, float* out, double* normpart,
+                           hipStream_t stream) {
   if (B <= 0) return hipSuccess;
   const int nblk = finalize_blocks(c);
   const int nkb = (c.K + 63) / 64;
   // the wide shape when its tiles alone give at least two workgroups per CU, else the narrow one
   const int nkc_w = (c.Kp + 255) / 256, ndb_w = (c.D + 3) / 4;
   if ((int64_t)B * nkc_w * ndb_w >= 512) {
-    hipLaunchKernelGGL((reduce_assemble_kernel<4, 256>), dim3(nkc_w * ndb_w, B),
-                       dim3(64 * red_waves(4, 256)), 0, stream, partials, frames, single, groups,
+    hipLaunchKernelGGL((reduce_assemble_kernel<4, 256, 4>), dim3(nkc_w * ndb_w, B),
+                       dim3(64 * red_waves(4, 256, 4)), 0, stream, partials, frames, single,
                        c.K, c.D, c.DP, c.Kp, nkc_w, nkb, c.mu64, c.isd64, c.ivar64, c.cu64,
                        c.cv64, flags, out, normpart, c.cnt);
   } else {
     const int nkc_n = (c.Kp + 63) / 64;
-    hipLaunchKernelGGL((reduce_assemble_kernel<1, 64>), dim3(nkc_n * c.D, B),
-                       dim3(64 * red_waves(1, 64)), 0, stream, partials, frames, single, groups,
+    hipLaunchKernelGGL((reduce_assemble_kernel<1, 64, 1>), dim3(nkc_n * c.D, B),
+                       dim3(64 * red_waves(1, 64, 1)), 0, stream, partials, frames, single,
                        c.K, c.D, c.DP, c.Kp, nkc_n, nkb, c.mu64, c.isd64, c.ivar64, c.cu64,
                        c.cv64, flags, out, normpart, c.cnt);
   }

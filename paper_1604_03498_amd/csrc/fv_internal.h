@@ -126,18 +126,19 @@ struct Item {
   int32_t pad;
 };
 
-// One frame for the finalize step: its descriptor count, its partial slots (items) and its
-// chunk groups (consecutive runs of at most kGroupItems slots reduced together).
+// One frame for the finalize step: its descriptor count, its partial slots (items), its place
+// in the batch (output row and norm parts) and its number of chunk groups: consecutive runs of
+// kGroupItems slots from item0 (the last one shorter), each summed (double, in index order)
+// before the group sums are added in order.
 struct Frame {
   int64_t nrows;
   int32_t item0;
   int32_t nitems;
-  int32_t group0;
+  int32_t index;
   int32_t ngroups;
 };
 
-// A chunk group: slots [item0, item0 + nitems) are summed (double, in index order) into one
-// row of the group buffer.
+// A chunk group: slots [item0, item0 + nitems).
 struct Group {
   int32_t item0;
   int32_t nitems;
@@ -198,13 +199,13 @@ int sliced_rows_per_wave_round(int DP);
 
 // Finalize: per frame, the slots of every chunk group are summed in index order in double
 // precision and the group sums are added in order; the totals are turned into u and v,
-// signed-square-rooted unless flagged off, and written to out[frame][2*K*D]; then L2
-// normalisation unless flagged off.  `frames` / `groups` are device tables, or null for one
-// frame (B == 1, `single`, groups of kGroupItems consecutive slots).  normpart holds
-// B * finalize_blocks(c) doubles.
+// signed-square-rooted unless flagged off, and written to out[index][2*K*D]; then L2
+// normalisation unless flagged off.  `frames` is a device table of B records (in any order:
+// the batch path puts the frames with the most slots first), or null for one frame (B == 1,
+// `single`).  normpart holds B * finalize_blocks(c) doubles.
 hipError_t launch_finalize(const Consts& c, const float* partials, const Frame* frames,
-                           Frame single, int B, const Group* groups, unsigned flags, float* out,
-                           double* normpart, hipStream_t stream);
+                           Frame single, int B, unsigned flags, float* out, double* normpart,
+                           hipStream_t stream);
 
 // Blocks per frame of the assembly step (size of normpart per frame).
 int finalize_blocks(const Consts& c);
