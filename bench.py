@@ -531,7 +531,7 @@ def main():
             tuned = {"batch_path": 1 if path_of(K, nb, n_cu, None) == "fused" else 2,
                      "batch_chunk": fv.get_tuning(hb)["batch_chunk"] or 1024, "trials": []}
         else:
-            tuned = autotune.tune_batch(hb, Xbd, offb, prec, stream=stream, reps=3,
+            tuned = autotune.tune_batch(hb, Xbd, offb, prec, stream=stream, reps=10,
                                         use_cache=False)
         bpath = {1: "fused", 2: "split"}[tuned["batch_path"]]
         log(f"[bench] batch form={form} tuned path={bpath} chunk={tuned['batch_chunk']} "
