@@ -48,10 +48,10 @@ TRAFFIC_JSON = os.path.join(HERE, "profiles", "hbm_traffic.json")
 STATS_KERNELS = {
     ("fp32", "split"): ["fused_f32_kernel<64, 8, true, false, true>", "sliced_f32_kernel<64, 8, false, true>"],
     ("fp32", "fused"): ["fused_f32_kernel<64, 8, false, false, false>"],
-    ("bf16_split", "split"): ["lse16_kernel<64, 8>", "sliced16_kernel<64, false>"],
-    ("bf16_split", "fused"): ["fused16p_kernel<64, false>"],
-    ("fp16_split", "split"): ["lse16_kernel<64, 8>", "sliced16_kernel<64, false>"],
-    ("fp16_split", "fused"): ["fused16p_kernel<64, false>"],
+    ("bf16_split", "split"): ["lse16_kernel<64, 8>", "sliced16r_kernel<64, false>"],
+    ("bf16_split", "fused"): ["fused16p_kernel<64, false, false>"],
+    ("fp16_split", "split"): ["lse16_kernel<64, 8>", "sliced16r_kernel<64, false>"],
+    ("fp16_split", "fused"): ["fused16p_kernel<64, false, false>"],
 }
 
 
