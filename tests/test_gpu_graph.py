@@ -210,3 +210,40 @@ def test_autotuner_keeps_results_within_tolerance(fv, tmp_path, monkeypatch, pre
     assert autotune.apply(h2, prec, int(off[-1]))
     assert fv.get_tuning(h2) == fv.get_tuning(h)
     assert np.array_equal(fv.encode_batch(h2, Xd, off, precision=prec).cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("graph", ["1", "0"], ids=["graph", "eager"])
+def test_back_to_back_batches_keep_their_tables(fv, graph, monkeypatch):
+    """Batches queued back to back on one stream without waiting (FV_ASYNC): the host builds
+    each call's work table in the staging half the call before last used, so it must not
+    overwrite a half whose copy has not run yet.  Every batch must equal the same batch encoded
+    alone, bitwise, whatever was queued around it."""
+    import torch
+    say(f"[gpu] back-to-back batches, FV_GRAPH={graph}")
+    monkeypatch.setenv("FV_GRAPH", graph)
+    g = fvsynth.gmm(256, 64, 2)
+    h = fv.gmm_load(g.weights, g.means, g.variances)
+    shapes = [[9000, 300, 4100], [1, 2, 3, 5000], [12000], [700, 700, 700, 700, 700, 700],
+              [0, 3000], [2500, 2501, 2502, 1023, 1025]]
+    data = [fvsynth.batch_frames(g, s, seed0=700 + 10 * i) for i, s in enumerate(shapes)]
+    stream = torch.cuda.Stream()
+    xs = [torch.from_numpy(X).cuda() for X, _ in data]
+    outs = [torch.full((off.size - 1, 2 * 256 * 64), -1.0, device="cuda") for _, off in data]
+    alone = []
+    for (X, off), Xd in zip(data, xs):
+        o = torch.empty(off.size - 1, 2 * 256 * 64, device="cuda")
+        fv.encode_batch(h, Xd, off, out=o, precision=1, stream=stream)
+        stream.synchronize()
+        alone.append(o.cpu().numpy())
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for i in range(len(data)):
+            fv.encode_batch(h, xs[i], data[i][1], out=outs[i], precision=1, flags=fv.ASYNC,
+                            stream=stream)
+        stream.synchronize()
+        for i in range(len(data)):
+            assert np.array_equal(outs[i].cpu().numpy(), alone[i]), (rep, shapes[i])
+            outs[i].fill_(-1.0)
+        torch.cuda.synchronize()
+    fv.stream_release(stream)
+    h.free()
