@@ -426,7 +426,8 @@ int fv_server_get_stats(fv_server* srv, fv_server_stats* st, int reset);
 
 /* Graph captures and replays of libfv's launch sequences since the process started, over all
  * devices and streams (monitoring: a capture instantiates a new executable graph, which costs
- * far more than a replay).  Batches on one stream share a graph while they fit its capacities
+ * far more than a replay).  Batches on one stream share two graphs (one per half of the
+ * double-buffered table staging, used by alternate calls) while they fit its capacities
  * (frames, chunks, rows; doubled when exceeded); single frames are keyed by their size. */
 int fv_graph_counters(int64_t* captures, int64_t* replays);
 
